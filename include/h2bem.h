@@ -1,0 +1,200 @@
+/*
+ * h2bem.h -- C interface of the MI355X (gfx950) H^2-matrix boundary element
+ * library for the 3-D Laplace equation.
+ *
+ * The library builds cluster and block trees for a flat triangle mesh,
+ * assembles the Galerkin single-layer matrix G and double-layer matrix K in
+ * H^2 form (interpolation far field, regularised-quadrature near field), and
+ * multiplies them with vectors on the GPU:
+ *
+ *   G (I x I): g_ij = int psi_i(x) int g(x,y) psi_j(y) dy dx       (paper, Section 1, eq. (slp))
+ *   K (I x J): k_ij = int psi_i(x) int dg/dn_y(x,y) phi_j(y) dy dx (paper, Section 1, eq. (dlp))
+ *   g(x,y) = 1 / (4 pi |x - y|)                                    (paper, Section 1)
+ *
+ * psi_i is the indicator of triangle i (index set I = triangles) and phi_j the
+ * continuous piecewise-linear hat function of vertex j (index set J =
+ * vertices), the discrete spaces chosen in Section 5.
+ *
+ * Conventions
+ *  - Every function returns an h2b_status; h2b_last_error() gives a message for
+ *    the last failing call on the calling thread.  No C++ exception crosses
+ *    this interface.  On error no output handle is written and no vector is
+ *    modified.
+ *  - Mesh arrays are host memory and are copied.  Vectors passed to the
+ *    products are device memory owned by the caller and are used
+ *    asynchronously on the given HIP stream (hipStream_t passed as void*; NULL
+ *    = the default stream); they must stay valid until the stream has passed
+ *    the call.  Vectors use the caller's numbering (triangle order for I,
+ *    vertex order for J); the cluster permutation is internal.
+ *  - Handles own their data.  A handle keeps alive everything it was built from
+ *    (an operator keeps its blocks, trees and mesh), so handles may be
+ *    destroyed in any order.
+ *  - Calls on one operator must not overlap in time on different streams: the
+ *    operator owns the intermediate vectors of its products.
+ */
+#ifndef H2BEM_H
+#define H2BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    H2B_OK = 0,
+    H2B_EINVAL = -1,   /* invalid argument (checked on the host before any launch) */
+    H2B_ENOMEM = -2,   /* host or device allocation failed */
+    H2B_EDEVICE = -3,  /* a HIP call failed */
+    H2B_ESTATE = -4,   /* handle in the wrong state for this call */
+    H2B_ENOTSUP = -5   /* valid request this build does not support */
+} h2b_status;
+
+typedef enum { H2B_P0 = 0, H2B_P1 = 1 } h2b_space;        /* triangles (I) / vertices (J) */
+typedef enum { H2B_SLP = 0, H2B_DLP = 1 } h2b_kernel;     /* G (P0 x P0) / K (P0 x P1) */
+typedef enum { H2B_F64 = 0, H2B_F32 = 1 } h2b_dtype;
+
+typedef struct h2b_mesh_s *h2b_mesh;
+typedef struct h2b_tree_s *h2b_tree;
+typedef struct h2b_blocks_s *h2b_blocks;
+typedef struct h2b_op_s *h2b_op;
+
+/* Thread-local text of the last error ("" if none). */
+const char *h2b_last_error(void);
+
+/* Library version string. */
+const char *h2b_version(void);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Flat triangle mesh (Section 5 uses such meshes of the unit sphere).
+ * vx, vy, vz: nv vertex coordinates; t0, t1, t2: nt triangles as 0-based
+ * vertex indices, counter-clockwise seen from outside (the outward normal is
+ * (v1-v0) x (v2-v0)).  All arrays are host memory and copied.
+ * Errors: H2B_EINVAL for nv < 3, nt < 1, an index out of range, a triangle with
+ * repeated vertices or zero area, or a non-finite coordinate. */
+h2b_status h2b_mesh_create(int64_t nv, const double *vx, const double *vy, const double *vz,
+                           int64_t nt, const int32_t *t0, const int32_t *t1, const int32_t *t2,
+                           h2b_mesh *out);
+h2b_status h2b_mesh_destroy(h2b_mesh mesh);
+
+/* ------------------------------------------------------------------ trees */
+
+/* Cluster tree (Section 2, Definition "Cluster tree") for the triangles (P0,
+ * characteristic point = centroid) or the vertices (P1, characteristic point =
+ * the vertex): the bounding box of a cluster's characteristic points is split
+ * at the midpoint of its longest side (ties: lowest axis; points on the plane
+ * go to the first child; if one side would be empty the next-longest axis is
+ * tried) while the cluster holds more than leaf_size indices.  Every cluster
+ * gets the axis-parallel box B_t of the supports of its basis functions
+ * (Section 3).  Host only.
+ * Errors: H2B_EINVAL for leaf_size < 1 or a bad space. */
+h2b_status h2b_tree_build(h2b_mesh mesh, h2b_space space, int leaf_size, h2b_tree *out);
+h2b_status h2b_tree_destroy(h2b_tree tree);
+
+/* Sizes of a tree: number of indices, clusters, leaves and levels. */
+h2b_status h2b_tree_info(h2b_tree tree, int64_t *n, int64_t *nclusters, int64_t *nleaves,
+                         int32_t *nlevels);
+
+/* Copies of a tree's arrays (host memory, caller-allocated):
+ *  perm[n]            original index at each position of the cluster order;
+ *  begin/end[nc]      index range perm[begin:end] of each cluster (pre-order,
+ *                     first child first);
+ *  parent[nc]         parent cluster (-1 for the root);
+ *  box[nc*6]          lo_x, lo_y, lo_z, hi_x, hi_y, hi_z of B_t.
+ * Any pointer may be NULL. */
+h2b_status h2b_tree_arrays(h2b_tree tree, int32_t *perm, int32_t *begin, int32_t *end,
+                           int32_t *parent, double *box);
+
+/* ----------------------------------------------------------------- blocks */
+
+/* Block tree (Section 2, Definition "Block tree") of rows x cols with the
+ * admissibility condition max(diam B_t, diam B_s) <= 2 eta dist(B_t, B_s)
+ * (Section 3, eq. (admissibility)): admissible blocks become farfield leaves,
+ * pairs of leaf clusters that are not admissible become nearfield leaves.
+ * far_disabled != 0 treats no block as admissible (every entry is then a
+ * nearfield entry: the dense Galerkin matrix).  Host only.
+ * Errors: H2B_EINVAL if the trees belong to different meshes, the rows tree is
+ * not P0, or eta <= 0. */
+h2b_status h2b_blocks_build(h2b_tree rows, h2b_tree cols, double eta, int far_disabled,
+                            h2b_blocks *out);
+h2b_status h2b_blocks_destroy(h2b_blocks blocks);
+
+/* Number of farfield and nearfield leaves and nearfield entries. */
+h2b_status h2b_blocks_info(h2b_blocks blocks, int64_t *nfar, int64_t *nnear,
+                           int64_t *near_entries);
+
+/* Copies of the leaf lists as cluster-id pairs (row, col), in the order of
+ * the recursive construction; caller-allocated 2*nfar / 2*nnear int32. */
+h2b_status h2b_blocks_lists(h2b_blocks blocks, int32_t *far_pairs, int32_t *near_pairs);
+
+/* --------------------------------------------------------------- assembly */
+
+typedef struct {
+    int order_m;            /* Chebyshev points per axis, k = m^3 per cluster; 1..6 */
+    int q_near;             /* Gauss points per dimension of the near-field quadrature; 1..16 */
+    double recompress_tol;  /* > 0: algebraic recompression of the cluster bases to this
+                               relative tolerance; 0: plain interpolation */
+    h2b_dtype farfield_dtype; /* storage/arithmetic of bases and coupling matrices */
+} h2b_params;
+
+/* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64. */
+void h2b_params_default(h2b_params *p);
+
+/* Assembles G (kernel H2B_SLP, cols tree P0) or K (H2B_DLP, cols tree P1) on
+ * the current HIP device, on hip_stream, and waits for it:
+ *  - near field: entries of every nearfield leaf by Sauter-Schwab regularised
+ *    quadrature with q_near^4 points per region (Section 5, Table 1);
+ *  - far field: m-th order tensor Chebyshev interpolation of g on B_t x B_s
+ *    (Section 3): G|ts ~ V_t S_ts W_s^T with (V_t)_{i nu} = int psi_i L_{t,nu},
+ *    S_ts = g(xi_{t,nu}, xi_{s,mu}), (W_s)_{j mu} = int psi_j L_{s,mu} for G and
+ *    int phi_j dL_{s,mu}/dn for K (derivative of the approximated kernel,
+ *    Section 5), with nested transfer matrices (Section 2, eq. (transfer)).
+ * Errors: H2B_EINVAL (parameters out of range, kernel/space mismatch),
+ * H2B_ENOMEM, H2B_EDEVICE. */
+h2b_status h2b_assemble(h2b_blocks blocks, h2b_kernel kernel, const h2b_params *params,
+                        void *hip_stream, h2b_op *out);
+h2b_status h2b_op_destroy(h2b_op op);
+
+typedef struct {
+    int64_t rows, cols;            /* matrix size */
+    int64_t nfar, nnear;           /* farfield / nearfield leaves */
+    int64_t near_entries;          /* stored nearfield entries */
+    int64_t coupling_entries;      /* stored coupling-matrix entries */
+    int64_t row_basis_entries;     /* leaf-basis + transfer entries, row tree */
+    int64_t col_basis_entries;     /* same, column tree (0 if shared with rows) */
+    int64_t bytes_near, bytes_far; /* device bytes of nearfield and farfield data */
+    int64_t bytes_vectors;         /* device bytes of the product's work vectors */
+    int32_t max_rank_row, max_rank_col;
+    double mean_rank_row, mean_rank_col;
+} h2b_op_stats;
+
+h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
+
+/* ---------------------------------------------------------------- product */
+
+/* y += alpha * op(A) * x for nrhs right-hand sides, A = G or K, op(A) = A
+ * (trans = 0) or A^T (trans = 1).  This is the H^2 matrix-vector product
+ * (Section 2): forward transformation (leaf bases, then transfer matrices up
+ * the column tree), coupling products over the farfield leaves, backward
+ * transformation down the row tree, and the nearfield blocks.
+ * x: device array of (trans ? rows : cols) x nrhs doubles, column j at x + j*ldx;
+ * y: device array of (trans ? cols : rows) x nrhs doubles, column j at y + j*ldy.
+ * Runs asynchronously on hip_stream.  x and y must not overlap.
+ * Errors: H2B_EINVAL (NULL pointers, nrhs < 1 or > 64, ld too small), H2B_EDEVICE. */
+h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
+                      double *y, int64_t ldy, int nrhs, void *hip_stream);
+
+/* Per-phase timing of the most recent h2b_matvec on an operator, in
+ * milliseconds, measured with HIP events on the product's own stream when
+ * timing was enabled by h2b_op_set_timing(op, 1).  phases[0..5] = gather,
+ * forward, coupling, backward, nearfield, scatter.  Waits for the events. */
+h2b_status h2b_op_set_timing(h2b_op op, int enable);
+h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[6]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2BEM_H */

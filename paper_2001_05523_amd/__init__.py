@@ -1,0 +1,239 @@
+"""Python binding of the gfx950 H^2 boundary element library (libh2bem.so).
+
+Argument marshalling only: every step of the assembly and of the products runs
+in the library's HIP kernels.  PyTorch supplies device memory (torch tensors
+for x and y) and streams.  The functions keep the C names of include/h2bem.h;
+``Mesh``, ``Tree``, ``Blocks`` and ``Operator`` are small owners of the handles.
+
+Importing this package loads the library and fails loudly if it has not been
+built (``python -m paper_2001_05523_amd.build``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+# torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+# first makes the library bind to that same runtime, so device pointers and
+# streams coming from torch are valid in the library: one process, one runtime.
+import torch  # noqa: F401  (load order matters)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libh2bem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libh2bem.so is not built: run `python -m paper_2001_05523_amd.build` "
+                      "(expected at %s)" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+H2B_OK, H2B_EINVAL, H2B_ENOMEM, H2B_EDEVICE, H2B_ESTATE, H2B_ENOTSUP = 0, -1, -2, -3, -4, -5
+H2B_P0, H2B_P1 = 0, 1
+H2B_SLP, H2B_DLP = 0, 1
+H2B_F64, H2B_F32 = 0, 1
+
+_i64, _i32, _dbl, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+class h2b_params(ctypes.Structure):
+    _fields_ = [("order_m", ctypes.c_int), ("q_near", ctypes.c_int),
+                ("recompress_tol", ctypes.c_double), ("farfield_dtype", ctypes.c_int)]
+
+
+class h2b_op_stats(ctypes.Structure):
+    _fields_ = [("rows", _i64), ("cols", _i64), ("nfar", _i64), ("nnear", _i64),
+                ("near_entries", _i64), ("coupling_entries", _i64),
+                ("row_basis_entries", _i64), ("col_basis_entries", _i64),
+                ("bytes_near", _i64), ("bytes_far", _i64), ("bytes_vectors", _i64),
+                ("max_rank_row", _i32), ("max_rank_col", _i32),
+                ("mean_rank_row", _dbl), ("mean_rank_col", _dbl)]
+
+
+_SIGS = {
+    "h2b_last_error": ([], ctypes.c_char_p),
+    "h2b_version": ([], ctypes.c_char_p),
+    "h2b_mesh_create": ([_i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _P(_vp)], ctypes.c_int),
+    "h2b_mesh_destroy": ([_vp], ctypes.c_int),
+    "h2b_tree_build": ([_vp, ctypes.c_int, ctypes.c_int, _P(_vp)], ctypes.c_int),
+    "h2b_tree_destroy": ([_vp], ctypes.c_int),
+    "h2b_tree_info": ([_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)], ctypes.c_int),
+    "h2b_tree_arrays": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_blocks_build": ([_vp, _vp, _dbl, ctypes.c_int, _P(_vp)], ctypes.c_int),
+    "h2b_blocks_destroy": ([_vp], ctypes.c_int),
+    "h2b_blocks_info": ([_vp, _P(_i64), _P(_i64), _P(_i64)], ctypes.c_int),
+    "h2b_blocks_lists": ([_vp, _vp, _vp], ctypes.c_int),
+    "h2b_params_default": ([_P(h2b_params)], None),
+    "h2b_assemble": ([_vp, ctypes.c_int, _P(h2b_params), _vp, _P(_vp)], ctypes.c_int),
+    "h2b_op_destroy": ([_vp], ctypes.c_int),
+    "h2b_op_info": ([_vp, _P(h2b_op_stats)], ctypes.c_int),
+    "h2b_matvec": ([_vp, ctypes.c_int, _dbl, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
+    "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f
+
+
+class H2BError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("h2bem error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(code):
+    if code != H2B_OK:
+        raise H2BError(code, _lib.h2b_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_vp)
+
+
+# --------------------------------------------------------------- handles
+
+class Mesh:
+    """Flat triangle mesh (host arrays copied into the library)."""
+
+    def __init__(self, verts, tris):
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, 3))
+        t = np.ascontiguousarray(np.asarray(tris).reshape(-1, 3)).astype(np.int32)
+        vx, vy, vz = (np.ascontiguousarray(v[:, d]) for d in range(3))
+        t0, t1, t2 = (np.ascontiguousarray(t[:, d]) for d in range(3))
+        h = _vp()
+        _check(h2b_mesh_create(len(v), _ptr(vx), _ptr(vy), _ptr(vz), len(t),
+                               _ptr(t0), _ptr(t1), _ptr(t2), ctypes.byref(h)))
+        self.handle = h
+        self.nv, self.nt = len(v), len(t)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            h2b_mesh_destroy(self.handle)
+            self.handle = None
+
+
+class Tree:
+    def __init__(self, mesh, space, leaf):
+        h = _vp()
+        _check(h2b_tree_build(mesh.handle, int(space), int(leaf), ctypes.byref(h)))
+        self.handle = h
+        n, nc, nl, lv = _i64(), _i64(), _i64(), _i32()
+        _check(h2b_tree_info(h, ctypes.byref(n), ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(lv)))
+        self.n, self.nclusters, self.nleaves, self.nlevels = n.value, nc.value, nl.value, lv.value
+
+    def arrays(self):
+        perm = np.zeros(self.n, dtype=np.int32)
+        b = np.zeros(self.nclusters, dtype=np.int32)
+        e = np.zeros(self.nclusters, dtype=np.int32)
+        par = np.zeros(self.nclusters, dtype=np.int32)
+        box = np.zeros((self.nclusters, 6))
+        _check(h2b_tree_arrays(self.handle, _ptr(perm), _ptr(b), _ptr(e), _ptr(par), _ptr(box)))
+        return dict(perm=perm, begin=b, end=e, parent=par, box=box)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            h2b_tree_destroy(self.handle)
+            self.handle = None
+
+
+class Blocks:
+    def __init__(self, rows, cols, eta=1.0, far_disabled=False):
+        h = _vp()
+        _check(h2b_blocks_build(rows.handle, cols.handle, float(eta), int(bool(far_disabled)),
+                                ctypes.byref(h)))
+        self.handle = h
+        nf, nn, ne = _i64(), _i64(), _i64()
+        _check(h2b_blocks_info(h, ctypes.byref(nf), ctypes.byref(nn), ctypes.byref(ne)))
+        self.nfar, self.nnear, self.near_entries = nf.value, nn.value, ne.value
+
+    def lists(self):
+        far = np.zeros((self.nfar, 2), dtype=np.int32)
+        near = np.zeros((self.nnear, 2), dtype=np.int32)
+        _check(h2b_blocks_lists(self.handle, _ptr(far), _ptr(near)))
+        return far, near
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            h2b_blocks_destroy(self.handle)
+            self.handle = None
+
+
+def default_params(**kw):
+    p = h2b_params()
+    h2b_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+class Operator:
+    """Assembled H^2 approximation of G (kernel 'slp') or K ('dlp').
+
+    ``op.matvec(x, y, alpha, trans)`` computes y += alpha op(A) x for torch
+    float64 CUDA tensors x, y of shape (n,) or (n, nrhs) (column-major as
+    produced by ``.t().contiguous().t()``, or nrhs = 1)."""
+
+    def __init__(self, verts=None, tris=None, kernel="slp", leaf=32, order_m=4, q_near=4,
+                 eta=1.0, far_disabled=False, recompress_tol=0.0, farfield_dtype="f64",
+                 stream=None, mesh=None):
+        self.mesh = mesh if mesh is not None else Mesh(verts, tris)
+        self.kernel = H2B_SLP if kernel == "slp" else H2B_DLP
+        self.rows = Tree(self.mesh, H2B_P0, leaf)
+        self.cols = self.rows if self.kernel == H2B_SLP else Tree(self.mesh, H2B_P1, leaf)
+        self.blocks = Blocks(self.rows, self.cols, eta, far_disabled)
+        p = default_params(order_m=order_m, q_near=q_near, recompress_tol=recompress_tol,
+                           farfield_dtype=H2B_F64 if farfield_dtype == "f64" else H2B_F32)
+        h = _vp()
+        _check(h2b_assemble(self.blocks.handle, self.kernel, ctypes.byref(p), _stream_ptr(stream),
+                            ctypes.byref(h)))
+        self.handle = h
+        self.shape = (self.mesh.nt, self.mesh.nt if self.kernel == H2B_SLP else self.mesh.nv)
+
+    def info(self):
+        s = h2b_op_stats()
+        _check(h2b_op_info(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def matvec(self, x, y, alpha=1.0, trans=False, stream=None):
+        import torch
+        nin = self.shape[0] if trans else self.shape[1]
+        nout = self.shape[1] if trans else self.shape[0]
+        for v, n, nm in ((x, nin, "x"), (y, nout, "y")):
+            if not isinstance(v, torch.Tensor) or v.dtype != torch.float64 or not v.is_cuda:
+                raise TypeError("%s must be a float64 CUDA tensor" % nm)
+            if v.shape[0] != n:
+                raise ValueError("%s has %d rows, expected %d" % (nm, v.shape[0], n))
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        ldx = x.shape[0] if x.dim() == 1 else x.stride(1)
+        ldy = y.shape[0] if y.dim() == 1 else y.stride(1)
+        if x.dim() == 2 and x.stride(0) != 1 or y.dim() == 2 and y.stride(0) != 1:
+            raise ValueError("x and y must be column-major")
+        _check(h2b_matvec(self.handle, int(bool(trans)), float(alpha), _vp(x.data_ptr()), ldx,
+                          _vp(y.data_ptr()), ldy, nrhs, _stream_ptr(stream)))
+        return y
+
+    def set_timing(self, on=True):
+        _check(h2b_op_set_timing(self.handle, int(bool(on))))
+
+    def phase_times(self):
+        out = np.zeros(6)
+        _check(h2b_op_phase_times(self.handle, _ptr(out)))
+        return dict(zip(("gather", "forward", "coupling", "backward", "nearfield", "scatter"), out))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            h2b_op_destroy(self.handle)
+            self.handle = None

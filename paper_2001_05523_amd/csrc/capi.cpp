@@ -1,0 +1,237 @@
+// extern "C" boundary of the library: handle management, argument checks and
+// translation of internal errors into h2b_status codes.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "op.hpp"
+
+struct h2b_mesh_s {
+    std::shared_ptr<h2b::Mesh> m;
+};
+struct h2b_tree_s {
+    std::shared_ptr<h2b::Tree> t;
+};
+struct h2b_blocks_s {
+    std::shared_ptr<h2b::Blocks> b;
+};
+struct h2b_op_s {
+    std::unique_ptr<h2b::Op> op;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F> h2b_status guarded(F &&f)
+{
+    try {
+        f();
+        g_err.clear();
+        return H2B_OK;
+    } catch (const h2b::Error &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return H2B_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return H2B_EINVAL;
+    } catch (...) {
+        g_err = "unknown error";
+        return H2B_EINVAL;
+    }
+}
+
+void need(const void *p, const char *what)
+{
+    if (!p) h2b::fail(H2B_EINVAL, std::string(what) + " is NULL");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h2b_last_error(void) { return g_err.c_str(); }
+
+const char *h2b_version(void) { return "h2bem 0.1 (gfx950)"; }
+
+h2b_status h2b_mesh_create(int64_t nv, const double *vx, const double *vy, const double *vz,
+                           int64_t nt, const int32_t *t0, const int32_t *t1, const int32_t *t2,
+                           h2b_mesh *out)
+{
+    return guarded([&] {
+        need(out, "out");
+        auto h = new h2b_mesh_s{h2b::make_mesh(nv, vx, vy, vz, nt, t0, t1, t2)};
+        *out = h;
+    });
+}
+
+h2b_status h2b_mesh_destroy(h2b_mesh mesh)
+{
+    delete mesh;
+    return H2B_OK;
+}
+
+h2b_status h2b_tree_build(h2b_mesh mesh, h2b_space space, int leaf_size, h2b_tree *out)
+{
+    return guarded([&] {
+        need(mesh, "mesh");
+        need(out, "out");
+        auto t = h2b::build_tree(mesh->m, space, leaf_size);
+        *out = new h2b_tree_s{t};
+    });
+}
+
+h2b_status h2b_tree_destroy(h2b_tree tree)
+{
+    delete tree;
+    return H2B_OK;
+}
+
+h2b_status h2b_tree_info(h2b_tree tree, int64_t *n, int64_t *nclusters, int64_t *nleaves,
+                         int32_t *nlevels)
+{
+    return guarded([&] {
+        need(tree, "tree");
+        const auto &T = *tree->t;
+        if (n) *n = T.n;
+        if (nclusters) *nclusters = T.nclusters();
+        if (nleaves) *nleaves = (int64_t)T.leaves.size();
+        if (nlevels) *nlevels = T.nlevels;
+    });
+}
+
+h2b_status h2b_tree_arrays(h2b_tree tree, int32_t *perm, int32_t *begin, int32_t *end,
+                           int32_t *parent, double *box)
+{
+    return guarded([&] {
+        need(tree, "tree");
+        const auto &T = *tree->t;
+        if (perm) std::memcpy(perm, T.perm.data(), sizeof(int32_t) * T.perm.size());
+        if (begin) std::memcpy(begin, T.begin.data(), sizeof(int32_t) * T.begin.size());
+        if (end) std::memcpy(end, T.end.data(), sizeof(int32_t) * T.end.size());
+        if (parent) std::memcpy(parent, T.parent.data(), sizeof(int32_t) * T.parent.size());
+        if (box) std::memcpy(box, T.box.data(), sizeof(double) * T.box.size());
+    });
+}
+
+h2b_status h2b_blocks_build(h2b_tree rows, h2b_tree cols, double eta, int far_disabled,
+                            h2b_blocks *out)
+{
+    return guarded([&] {
+        need(rows, "rows");
+        need(cols, "cols");
+        need(out, "out");
+        auto b = h2b::build_blocks(rows->t, cols->t, eta, far_disabled != 0);
+        *out = new h2b_blocks_s{b};
+    });
+}
+
+h2b_status h2b_blocks_destroy(h2b_blocks blocks)
+{
+    delete blocks;
+    return H2B_OK;
+}
+
+h2b_status h2b_blocks_info(h2b_blocks blocks, int64_t *nfar, int64_t *nnear, int64_t *near_entries)
+{
+    return guarded([&] {
+        need(blocks, "blocks");
+        const auto &B = *blocks->b;
+        if (nfar) *nfar = (int64_t)B.far_t.size();
+        if (nnear) *nnear = (int64_t)B.near_t.size();
+        if (near_entries) {
+            int64_t s = 0;
+            for (size_t i = 0; i < B.near_t.size(); ++i)
+                s += (int64_t)B.rows->size(B.near_t[i]) * B.cols->size(B.near_s[i]);
+            *near_entries = s;
+        }
+    });
+}
+
+h2b_status h2b_blocks_lists(h2b_blocks blocks, int32_t *far_pairs, int32_t *near_pairs)
+{
+    return guarded([&] {
+        need(blocks, "blocks");
+        const auto &B = *blocks->b;
+        if (far_pairs)
+            for (size_t i = 0; i < B.far_t.size(); ++i) {
+                far_pairs[2 * i] = B.far_t[i];
+                far_pairs[2 * i + 1] = B.far_s[i];
+            }
+        if (near_pairs)
+            for (size_t i = 0; i < B.near_t.size(); ++i) {
+                near_pairs[2 * i] = B.near_t[i];
+                near_pairs[2 * i + 1] = B.near_s[i];
+            }
+    });
+}
+
+void h2b_params_default(h2b_params *p)
+{
+    if (!p) return;
+    p->order_m = 4;
+    p->q_near = 4;
+    p->recompress_tol = 0.0;
+    p->farfield_dtype = H2B_F64;
+}
+
+h2b_status h2b_assemble(h2b_blocks blocks, h2b_kernel kernel, const h2b_params *params,
+                        void *hip_stream, h2b_op *out)
+{
+    return guarded([&] {
+        need(blocks, "blocks");
+        need(params, "params");
+        need(out, "out");
+        auto op = h2b::assemble_op(blocks->b, kernel, *params, static_cast<hipStream_t>(hip_stream));
+        *out = new h2b_op_s{std::move(op)};
+    });
+}
+
+h2b_status h2b_op_destroy(h2b_op op)
+{
+    delete op;
+    return H2B_OK;
+}
+
+h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out)
+{
+    return guarded([&] {
+        need(op, "op");
+        need(out, "out");
+        h2b::op_stats(*op->op, *out);
+    });
+}
+
+h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx, double *y,
+                      int64_t ldy, int nrhs, void *hip_stream)
+{
+    return guarded([&] {
+        need(op, "op");
+        h2b::matvec(*op->op, trans ? 1 : 0, alpha, x, ldx, y, ldy, nrhs,
+                    static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_op_set_timing(h2b_op op, int enable)
+{
+    return guarded([&] {
+        need(op, "op");
+        op->op->timing = enable != 0;
+        op->op->timed_valid = false;
+    });
+}
+
+h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[6])
+{
+    return guarded([&] {
+        need(op, "op");
+        need(phases_ms, "phases_ms");
+        h2b::phase_times(*op->op, phases_ms);
+    });
+}
+
+}  // extern "C"

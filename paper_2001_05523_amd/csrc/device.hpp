@@ -1,0 +1,74 @@
+// Device-side inputs and kernel launchers of the H^2 library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "panels.hpp"
+
+namespace h2b {
+
+constexpr int QMAX = 16;   // largest Gauss order per dimension
+constexpr int MMAX = 6;    // largest Chebyshev order per axis
+
+// Mesh in device memory (structure of arrays).
+struct GeoDev {
+    const double *vx, *vy, *vz;
+    const int32_t *t0, *t1, *t2;
+    const double *nx, *ny, *nz;
+    const int64_t *vt_ptr;
+    const int32_t *vt_idx;
+};
+
+// Gauss-Legendre rule on [0,1], passed by value to the kernels.
+struct QuadDev {
+    int q;
+    double t[QMAX];
+    double w[QMAX];
+};
+
+// ------------------------------------------------------------- assembly
+
+// Nearfield entries of every group of rp (one workgroup per group).
+// kernel H2B_SLP: vals = G_ij; H2B_DLP: vals = K_ij (column j = vertex).
+void launch_near_assemble(h2b_kernel kernel, const RowPanels &rp, const int32_t *rperm,
+                          const int32_t *cperm, const GeoDev &geo, const QuadDev &quad,
+                          double *vals, hipStream_t st);
+
+// Leaf bases stored as V_t^T (k x |t| per leaf group of rp).
+// space P0: (V_t)_{i nu} = int_{tau_i} L_{t,nu};
+// dlp_cols (space P1): (W_t)_{j nu} = sum_{tau around j} int_tau phi_j dL_{t,nu}/dn_tau.
+template <typename T>
+void launch_leaf_basis(bool dlp_cols, const RowPanels &rp, const int32_t *perm,
+                       const double *axes, int m, const GeoDev &geo, const QuadDev &quad,
+                       T *vals, hipStream_t st);
+
+// Transfer panels [E_c0^T | E_c1^T], (E_c)_{mu nu} = L_{t,nu}(xi_{c,mu}).
+template <typename T>
+void launch_transfer(const RowPanels &rp, const double *axes, int m, T *vals, hipStream_t st);
+
+// Coupling panels, S_ts[nu, mu] = g(xi_{t,nu}, xi_{s,mu}).
+template <typename T>
+void launch_coupling(const RowPanels &rp, const double *raxes, const double *caxes, int m, T *vals,
+                     hipStream_t st);
+
+// --------------------------------------------------------------- product
+
+// y[out_begin + r] (=|+=) sum_c vals[...] x[...] for groups [g0, g1).
+template <typename VT, typename XT, typename YT>
+void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
+                     bool accumulate, hipStream_t st);
+
+// y[out_begin + j] += sum over blocks of the transposed product, groups [g0, g1).
+template <typename VT, typename XT, typename YT>
+void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
+                     hipStream_t st);
+
+// xp[k + c*n] = x[perm[k] + c*ldx]
+void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,
+                   double *xp, hipStream_t st);
+// y[perm[k] + c*ldy] += alpha * yp[k + c*n]
+void launch_scatter_add(const int32_t *perm, int64_t n, int nrhs, double alpha, const double *yp,
+                        double *y, int64_t ldy, hipStream_t st);
+template <typename T> void launch_fill_zero(T *p, int64_t n, hipStream_t st);
+
+}  // namespace h2b

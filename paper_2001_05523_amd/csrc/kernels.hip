@@ -1,0 +1,709 @@
+// HIP kernels for gfx950: nearfield quadrature, interpolation bases, transfer
+// and coupling matrices, and the panel products that make up the H^2
+// matrix-vector product.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.hpp"
+
+namespace h2b {
+
+namespace {
+
+constexpr double INV_4PI = 0.0795774715459476678844418816862571810;  // 1 / (4 pi)
+constexpr int NT = 256;                                             // threads per workgroup
+
+inline int blocks_for(int64_t n, int per = NT)
+{
+    int64_t b = (n + per - 1) / per;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1 << 20);
+}
+
+// ===================================================================
+//  Triangle-pair quadrature (paper, Section 5: Sauter-Schwab-Erichsen)
+// ===================================================================
+//
+// A flat triangle with ordered corners (P0,P1,P2) is parametrised over the
+// reference triangle {0 <= u2 <= u1 <= 1} by P0 + u1 (P1-P0) + u2 (P2-P1).
+// For a touching pair both triangles start at the shared corner, so every
+// Sauter-Schwab substitution has the form x = xi X(eta), y = xi Y(eta) in
+// reference coordinates with Jacobian xi^3 J(eta), and the physical difference
+// is x - y = xi D(eta).  The integrands of G and K are then polynomials of
+// degree <= 2 in xi divided by |D|, so the xi-direction of the tensor Gauss
+// rule is exact and is summed in closed form; the remaining three directions
+// use the q-point Gauss rule per dimension.
+
+struct Tri {
+    double p[3];   // first corner
+    double e1[3];  // P1 - P0
+    double e2[3];  // P2 - P1
+};
+
+__device__ inline void load_tri(const GeoDev &g, int c0, int c1, int c2, Tri &T)
+{
+    double a[3] = {g.vx[c0], g.vy[c0], g.vz[c0]};
+    double b[3] = {g.vx[c1], g.vy[c1], g.vz[c1]};
+    double c[3] = {g.vx[c2], g.vy[c2], g.vz[c2]};
+    for (int d = 0; d < 3; ++d) {
+        T.p[d] = a[d];
+        T.e1[d] = b[d] - a[d];
+        T.e2[d] = c[d] - b[d];
+    }
+}
+
+__device__ inline double tri_jac(const Tri &T)
+{
+    double c0 = T.e1[1] * T.e2[2] - T.e1[2] * T.e2[1];
+    double c1 = T.e1[2] * T.e2[0] - T.e1[0] * T.e2[2];
+    double c2 = T.e1[0] * T.e2[1] - T.e1[1] * T.e2[0];
+    return sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+}
+
+// Reference directions X(eta), Y(eta) and J(eta) of region r of the relation
+// with ns shared vertices (3: six regions, 2: five regions, 1: two regions).
+__device__ inline double ss_dirs(int ns, int r, double a, double b, double c, double X[2],
+                                 double Y[2])
+{
+    const double ab = a * b, abc = a * b * c;
+    if (ns == 3) {
+        switch (r) {
+        case 0: X[0] = 1.0; X[1] = 1.0 - a + ab; Y[0] = 1.0 - abc; Y[1] = 1.0 - a; break;
+        case 1: X[0] = 1.0 - abc; X[1] = 1.0 - a; Y[0] = 1.0; Y[1] = 1.0 - a + ab; break;
+        case 2: X[0] = 1.0; X[1] = a * (1.0 - b + b * c); Y[0] = 1.0 - ab; Y[1] = a * (1.0 - b); break;
+        case 3: X[0] = 1.0 - ab; X[1] = a * (1.0 - b); Y[0] = 1.0; Y[1] = a * (1.0 - b + b * c); break;
+        case 4: X[0] = 1.0 - abc; X[1] = a * (1.0 - b * c); Y[0] = 1.0; Y[1] = a * (1.0 - b); break;
+        default: X[0] = 1.0; X[1] = a * (1.0 - b); Y[0] = 1.0 - abc; Y[1] = a * (1.0 - b * c); break;
+        }
+        return a * a * b;
+    }
+    if (ns == 2) {
+        switch (r) {
+        case 0: X[0] = 1.0; X[1] = a * c; Y[0] = 1.0 - ab; Y[1] = a * (1.0 - b); return a * a;
+        case 1: X[0] = 1.0; X[1] = a; Y[0] = 1.0 - abc; Y[1] = ab * (1.0 - c); break;
+        case 2: X[0] = 1.0 - ab; X[1] = a * (1.0 - b); Y[0] = 1.0; Y[1] = abc; break;
+        case 3: X[0] = 1.0 - abc; X[1] = ab * (1.0 - c); Y[0] = 1.0; Y[1] = a; break;
+        default: X[0] = 1.0 - abc; X[1] = a * (1.0 - b * c); Y[0] = 1.0; Y[1] = ab; break;
+        }
+        return a * a * b;
+    }
+    if (r == 0) {
+        X[0] = 1.0; X[1] = a; Y[0] = b; Y[1] = b * c;
+    } else {
+        X[0] = b; X[1] = b * c; Y[0] = 1.0; Y[1] = a;
+    }
+    return b;
+}
+
+// Corner order of a pair: returns the number of shared vertices; ox/oy are the
+// stored corner slots in quadrature order (shared corners first: a common edge
+// in increasing global vertex index, a common vertex followed by the rest in
+// the triangle's cyclic order).
+__device__ inline int pair_slots(const int vx[3], const int vy[3], int ox[3], int oy[3])
+{
+    int ns = 0, sx[3], sy[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if (vx[a] == vy[b]) {
+                sx[ns] = a;
+                sy[ns] = b;
+                ++ns;
+            }
+    if (ns == 2) {
+        int f = (vx[sx[0]] < vx[sx[1]]) ? 0 : 1;
+        ox[0] = sx[f]; ox[1] = sx[1 - f]; ox[2] = 3 - sx[0] - sx[1];
+        oy[0] = sy[f]; oy[1] = sy[1 - f]; oy[2] = 3 - sy[0] - sy[1];
+    } else if (ns == 1) {
+        for (int a = 0; a < 3; ++a) {
+            ox[a] = (sx[0] + a) % 3;
+            oy[a] = (sy[0] + a) % 3;
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) ox[a] = oy[a] = a;
+    }
+    return ns;
+}
+
+// int_X int_Y g(x,y) dy dx for a touching pair (ns >= 1).
+__device__ double slp_touching(int ns, const Tri &X, const Tri &Y, const QuadDev &Q)
+{
+    const int nreg = (ns == 3) ? 6 : (ns == 2) ? 5 : 2;
+    double acc = 0.0;
+    for (int r = 0; r < nreg; ++r)
+        for (int i = 0; i < Q.q; ++i)
+            for (int j = 0; j < Q.q; ++j) {
+                const double wij = Q.w[i] * Q.w[j];
+                for (int k = 0; k < Q.q; ++k) {
+                    double xd[2], yd[2];
+                    double jac = ss_dirs(ns, r, Q.t[i], Q.t[j], Q.t[k], xd, yd);
+                    double D0 = xd[0] * X.e1[0] + xd[1] * X.e2[0] - yd[0] * Y.e1[0] - yd[1] * Y.e2[0];
+                    double D1 = xd[0] * X.e1[1] + xd[1] * X.e2[1] - yd[0] * Y.e1[1] - yd[1] * Y.e2[1];
+                    double D2 = xd[0] * X.e1[2] + xd[1] * X.e2[2] - yd[0] * Y.e1[2] - yd[1] * Y.e2[2];
+                    acc += wij * Q.w[k] * jac * rsqrt(D0 * D0 + D1 * D1 + D2 * D2);
+                }
+            }
+    // xi^3 / xi integrated over [0,1]
+    return acc * (1.0 / 3.0);
+}
+
+// int_X int_Y dg/dn_y(x,y) lambda_c(y) dy dx for a touching pair, c = corner of
+// Y in quadrature order; ny = unit normal of Y.
+__device__ double dlp_touching(int ns, const Tri &X, const Tri &Y, const double ny[3], int c,
+                               const QuadDev &Q)
+{
+    if (ns == 3) return 0.0;  // x - y lies in the plane of the triangle
+    const int nreg = (ns == 2) ? 5 : 2;
+    double acc = 0.0;
+    for (int r = 0; r < nreg; ++r)
+        for (int i = 0; i < Q.q; ++i)
+            for (int j = 0; j < Q.q; ++j) {
+                const double wij = Q.w[i] * Q.w[j];
+                for (int k = 0; k < Q.q; ++k) {
+                    double xd[2], yd[2];
+                    double jac = ss_dirs(ns, r, Q.t[i], Q.t[j], Q.t[k], xd, yd);
+                    double D0 = xd[0] * X.e1[0] + xd[1] * X.e2[0] - yd[0] * Y.e1[0] - yd[1] * Y.e2[0];
+                    double D1 = xd[0] * X.e1[1] + xd[1] * X.e2[1] - yd[0] * Y.e1[1] - yd[1] * Y.e2[1];
+                    double D2 = xd[0] * X.e1[2] + xd[1] * X.e2[2] - yd[0] * Y.e1[2] - yd[1] * Y.e2[2];
+                    double ir = rsqrt(D0 * D0 + D1 * D1 + D2 * D2);
+                    double kern = (D0 * ny[0] + D1 * ny[1] + D2 * ny[2]) * ir * ir * ir;
+                    // barycentric weight of corner c at y = xi Y, integrated against xi
+                    double lam = (c == 0) ? (0.5 - yd[0] * (1.0 / 3.0))
+                               : (c == 1) ? (yd[0] - yd[1]) * (1.0 / 3.0)
+                                          : yd[1] * (1.0 / 3.0);
+                    acc += wij * Q.w[k] * jac * kern * lam;
+                }
+            }
+    return acc;
+}
+
+// Disjoint pair: collapsed Gauss rule on each triangle (q^2 points each).
+// c < 0: single layer; c in 0..2: double layer with barycentric weight of
+// corner c of Y.
+__device__ double pair_regular(const Tri &X, const Tri &Y, const double ny[3], int c,
+                               const QuadDev &Q)
+{
+    double acc = 0.0;
+    for (int i = 0; i < Q.q; ++i) {
+        const double u = Q.t[i];
+        for (int j = 0; j < Q.q; ++j) {
+            const double v = u * Q.t[j];
+            const double wx = Q.w[i] * Q.w[j] * u;
+            const double x0 = X.p[0] + u * X.e1[0] + v * X.e2[0];
+            const double x1 = X.p[1] + u * X.e1[1] + v * X.e2[1];
+            const double x2 = X.p[2] + u * X.e1[2] + v * X.e2[2];
+            double inner = 0.0;
+            for (int k = 0; k < Q.q; ++k) {
+                const double s = Q.t[k];
+                const double ws = Q.w[k] * s;
+                for (int l = 0; l < Q.q; ++l) {
+                    const double sv = s * Q.t[l];
+                    const double d0 = x0 - (Y.p[0] + s * Y.e1[0] + sv * Y.e2[0]);
+                    const double d1 = x1 - (Y.p[1] + s * Y.e1[1] + sv * Y.e2[1]);
+                    const double d2 = x2 - (Y.p[2] + s * Y.e1[2] + sv * Y.e2[2]);
+                    const double ir = rsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    double f;
+                    if (c < 0) {
+                        f = ir;
+                    } else {
+                        const double lam = (c == 0) ? 1.0 - s : (c == 1) ? s - sv : sv;
+                        f = (d0 * ny[0] + d1 * ny[1] + d2 * ny[2]) * ir * ir * ir * lam;
+                    }
+                    inner += ws * Q.w[l] * f;
+                }
+            }
+            acc += wx * inner;
+        }
+    }
+    return acc;
+}
+
+__device__ double slp_entry(const GeoDev &g, int i, int j, const QuadDev &Q)
+{
+    int vi[3] = {g.t0[i], g.t1[i], g.t2[i]};
+    int vj[3] = {g.t0[j], g.t1[j], g.t2[j]};
+    int oi[3], oj[3];
+    int ns = pair_slots(vi, vj, oi, oj);
+    Tri X, Y;
+    load_tri(g, vi[oi[0]], vi[oi[1]], vi[oi[2]], X);
+    load_tri(g, vj[oj[0]], vj[oj[1]], vj[oj[2]], Y);
+    double jj = tri_jac(X) * tri_jac(Y) * INV_4PI;
+    double nn[3] = {0, 0, 0};
+    double v = (ns == 0) ? pair_regular(X, Y, nn, -1, Q) : slp_touching(ns, X, Y, Q);
+    return v * jj;
+}
+
+// Contribution of triangle tj to K_{i, vertex} where vertex sits in stored slot
+// `slot` of tj.
+__device__ double dlp_part(const GeoDev &g, int i, int tj, int slot, const QuadDev &Q)
+{
+    int vi[3] = {g.t0[i], g.t1[i], g.t2[i]};
+    int vj[3] = {g.t0[tj], g.t1[tj], g.t2[tj]};
+    int oi[3], oj[3];
+    int ns = pair_slots(vi, vj, oi, oj);
+    int c = (oj[0] == slot) ? 0 : (oj[1] == slot) ? 1 : 2;
+    Tri X, Y;
+    load_tri(g, vi[oi[0]], vi[oi[1]], vi[oi[2]], X);
+    load_tri(g, vj[oj[0]], vj[oj[1]], vj[oj[2]], Y);
+    double ny[3] = {g.nx[tj], g.ny[tj], g.nz[tj]};
+    double jj = tri_jac(X) * tri_jac(Y) * INV_4PI;
+    double v = (ns == 0) ? pair_regular(X, Y, ny, c, Q) : dlp_touching(ns, X, Y, ny, c, Q);
+    return v * jj;
+}
+
+// Column position of panel column c: walk the group's segments.
+__device__ inline int panel_column(const RowPanelDev &d, int g, int c)
+{
+    int s = d.seg_ptr[g];
+    const int s1 = d.seg_ptr[g + 1];
+    while (s + 1 < s1 && c >= d.seg_len[s]) {
+        c -= d.seg_len[s];
+        ++s;
+    }
+    return d.seg_in[s] + c;
+}
+
+template <int KER>
+__global__ __launch_bounds__(NT) void k_near_assemble(RowPanelDev d, const int32_t *__restrict__ rperm,
+                                                      const int32_t *__restrict__ cperm, GeoDev geo,
+                                                      QuadDev Q, double *__restrict__ vals)
+{
+    const int g = blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int ob = d.out_begin[g];
+    const int64_t off = d.val_off[g];
+    const int64_t n = (int64_t)nr * nc;
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+        const int r = (int)(e / nc), c = (int)(e % nc);
+        const int i = rperm[ob + r];
+        const int j = cperm[panel_column(d, g, c)];
+        double v;
+        if (KER == 0) {
+            v = slp_entry(geo, i, j, Q);
+        } else {
+            v = 0.0;
+            for (int64_t a = geo.vt_ptr[j]; a < geo.vt_ptr[j + 1]; ++a) {
+                const int tj = geo.vt_idx[a];
+                const int slot = (geo.t0[tj] == j) ? 0 : (geo.t1[tj] == j) ? 1 : 2;
+                v += dlp_part(geo, i, tj, slot, Q);
+            }
+        }
+        vals[off + e] = v;
+    }
+}
+
+// ===================================================================
+//  Interpolation: Lagrange polynomials on Chebyshev points (Section 3)
+// ===================================================================
+
+// ell_a(z) on the m points pts.
+__device__ inline double lag1(const double *pts, int m, int a, double z)
+{
+    double v = 1.0;
+    for (int b = 0; b < m; ++b)
+        if (b != a) v *= (z - pts[b]) / (pts[a] - pts[b]);
+    return v;
+}
+
+// d ell_a / dz.
+__device__ inline double lag1d(const double *pts, int m, int a, double z)
+{
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) {
+        if (k == a) continue;
+        double v = 1.0 / (pts[a] - pts[k]);
+        for (int b = 0; b < m; ++b)
+            if (b != a && b != k) v *= (z - pts[b]) / (pts[a] - pts[b]);
+        s += v;
+    }
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_leaf_basis(bool dlp_cols, RowPanelDev d,
+                                                   const int32_t *__restrict__ perm,
+                                                   const double *__restrict__ axes, int m,
+                                                   GeoDev geo, QuadDev Q, T *__restrict__ vals)
+{
+    const int g = blockIdx.x;
+    const int cl = d.tag[g];
+    const int k = d.nrows[g], nc = d.ncols[g];
+    const int in0 = d.seg_in[d.seg_ptr[g]];
+    const int64_t off = d.val_off[g];
+    __shared__ double ax[3 * MMAX];
+    if (threadIdx.x < 3 * m) ax[threadIdx.x] = axes[(int64_t)cl * 3 * m + threadIdx.x];
+    __syncthreads();
+    const int64_t n = (int64_t)k * nc;
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+        const int nu = (int)(e / nc), r = (int)(e % nc);
+        const int n1 = nu % m, n2 = (nu / m) % m, n3 = nu / (m * m);
+        const int idx = perm[in0 + r];
+        double acc = 0.0;
+        auto one_triangle = [&](int tri, int slot) {
+            Tri tr;
+            load_tri(geo, geo.t0[tri], geo.t1[tri], geo.t2[tri], tr);
+            const double J = tri_jac(tr);
+            double s = 0.0;
+            for (int a = 0; a < Q.q; ++a) {
+                const double u = Q.t[a];
+                for (int b = 0; b < Q.q; ++b) {
+                    const double v = u * Q.t[b];
+                    const double w = Q.w[a] * Q.w[b] * u;
+                    const double x = tr.p[0] + u * tr.e1[0] + v * tr.e2[0];
+                    const double y = tr.p[1] + u * tr.e1[1] + v * tr.e2[1];
+                    const double z = tr.p[2] + u * tr.e1[2] + v * tr.e2[2];
+                    const double l1 = lag1(ax, m, n1, x), l2 = lag1(ax + m, m, n2, y),
+                                 l3 = lag1(ax + 2 * m, m, n3, z);
+                    if (slot < 0) {
+                        s += w * l1 * l2 * l3;
+                    } else {
+                        const double lam = (slot == 0) ? 1.0 - u : (slot == 1) ? u - v : v;
+                        const double g1 = lag1d(ax, m, n1, x) * l2 * l3;
+                        const double g2 = l1 * lag1d(ax + m, m, n2, y) * l3;
+                        const double g3 = l1 * l2 * lag1d(ax + 2 * m, m, n3, z);
+                        s += w * lam * (g1 * geo.nx[tri] + g2 * geo.ny[tri] + g3 * geo.nz[tri]);
+                    }
+                }
+            }
+            acc += J * s;
+        };
+        if (!dlp_cols) {
+            one_triangle(idx, -1);
+        } else {
+            for (int64_t a = geo.vt_ptr[idx]; a < geo.vt_ptr[idx + 1]; ++a) {
+                const int tri = geo.vt_idx[a];
+                const int slot = (geo.t0[tri] == idx) ? 0 : (geo.t1[tri] == idx) ? 1 : 2;
+                one_triangle(tri, slot);
+            }
+        }
+        vals[off + nu * (int64_t)nc + r] = (T)acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_transfer(RowPanelDev d, const double *__restrict__ axes,
+                                                 int m, T *__restrict__ vals)
+{
+    const int g = blockIdx.x;
+    const int t = d.tag[g];
+    const int k = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const double *pt = axes + (int64_t)t * 3 * m;
+    const int64_t n = (int64_t)k * nc;
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+        const int nu = (int)(e / nc);
+        int c = (int)(e % nc);
+        int s = s0;
+        while (s + 1 < s1 && c >= d.seg_len[s]) {
+            c -= d.seg_len[s];
+            ++s;
+        }
+        const double *pc = axes + (int64_t)d.seg_tag[s] * 3 * m;
+        const int mu = c;
+        const double v = lag1(pt, m, nu % m, pc[mu % m]) *
+                         lag1(pt + m, m, (nu / m) % m, pc[m + (mu / m) % m]) *
+                         lag1(pt + 2 * m, m, nu / (m * m), pc[2 * m + mu / (m * m)]);
+        vals[off + e] = (T)v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_coupling(RowPanelDev d, const double *__restrict__ raxes,
+                                                 const double *__restrict__ caxes, int m,
+                                                 T *__restrict__ vals)
+{
+    const int g = blockIdx.x;
+    const int t = d.tag[g];
+    const int k = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const double *pt = raxes + (int64_t)t * 3 * m;
+    const int64_t n = (int64_t)k * nc;
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+        const int nu = (int)(e / nc);
+        int c = (int)(e % nc);
+        int s = s0;
+        while (s + 1 < s1 && c >= d.seg_len[s]) {
+            c -= d.seg_len[s];
+            ++s;
+        }
+        const double *ps = caxes + (int64_t)d.seg_tag[s] * 3 * m;
+        const int mu = c;
+        const double dx = pt[nu % m] - ps[mu % m];
+        const double dy = pt[m + (nu / m) % m] - ps[m + (mu / m) % m];
+        const double dz = pt[2 * m + nu / (m * m)] - ps[2 * m + mu / (m * m)];
+        vals[off + e] = (T)(INV_4PI * rsqrt(dx * dx + dy * dy + dz * dz));
+    }
+}
+
+// ===================================================================
+//  Panel products
+// ===================================================================
+
+template <typename T> struct Acc { using type = double; };
+template <> struct Acc<float> { using type = float; };
+
+template <typename A> __device__ inline A wave_sum(A v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int CHUNK = 4096;  // input columns staged in LDS per pass
+
+// One workgroup per group: stage the input segments of a column chunk in LDS,
+// then every wave takes rows round-robin and streams its row of the panel with
+// coalesced loads; per-row partial sums live in LDS across chunks.
+template <typename VT, typename XT, typename YT>
+__global__ __launch_bounds__(NT) void k_rowpanel(RowPanelDev d, int g0, const VT *__restrict__ vals,
+                                                 const XT *__restrict__ x, YT *__restrict__ y,
+                                                 int accumulate)
+{
+    using A = typename Acc<VT>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *xs = reinterpret_cast<A *>(smem_raw);
+    A *racc = xs + CHUNK;
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int sp0 = d.seg_ptr[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = NT / 64;
+
+    int seg = sp0, seg_pos = 0;  // staging cursor over the segments
+    for (int c0 = 0; c0 < nc; c0 += CHUNK) {
+        const int clen = min(CHUNK, nc - c0);
+        // stage columns [c0, c0 + clen)
+        {
+            int filled = 0;
+            int s = seg, p = seg_pos;
+            while (filled < clen) {
+                const int len = min(d.seg_len[s] - p, clen - filled);
+                const XT *src = x + d.seg_in[s] + p;
+                for (int j = threadIdx.x; j < len; j += NT) xs[filled + j] = (A)src[j];
+                filled += len;
+                p += len;
+                if (p == d.seg_len[s]) {
+                    ++s;
+                    p = 0;
+                }
+            }
+            seg = s;
+            seg_pos = p;
+        }
+        __syncthreads();
+        for (int r = wave; r < nr; r += NW) {
+            const VT *row = vals + off + (int64_t)r * nc + c0;
+            A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            int c = lane;
+            for (; c + 192 < clen; c += 256) {
+                s0 += (A)row[c] * xs[c];
+                s1 += (A)row[c + 64] * xs[c + 64];
+                s2 += (A)row[c + 128] * xs[c + 128];
+                s3 += (A)row[c + 192] * xs[c + 192];
+            }
+            for (; c < clen; c += 64) s0 += (A)row[c] * xs[c];
+            A s = wave_sum((s0 + s1) + (s2 + s3));
+            if (lane == 0) racc[r] = (c0 == 0) ? s : racc[r] + s;
+        }
+        __syncthreads();
+    }
+    const int ob = d.out_begin[g];
+    for (int r = threadIdx.x; r < nr; r += NT) {
+        const A v = (nc > 0) ? racc[r] : A(0);
+        if (accumulate)
+            y[ob + r] = (YT)((A)y[ob + r] + v);
+        else
+            y[ob + r] = (YT)v;
+    }
+}
+
+// One workgroup per output segment: lanes over output entries (64 at a time),
+// waves over the rows of all contributing blocks, partial sums reduced in LDS.
+template <typename VT, typename XT, typename YT>
+__global__ __launch_bounds__(NT) void k_colpanel(ColPanelDev d, int g0, const VT *__restrict__ vals,
+                                                 const XT *__restrict__ x, YT *__restrict__ y)
+{
+    using A = typename Acc<VT>::type;
+    constexpr int NW = NT / 64;
+    __shared__ A red[NW][64];
+    const int g = g0 + blockIdx.x;
+    const int ob = d.out_begin[g], ol = d.out_len[g];
+    const int b0 = d.blk_ptr[g], b1 = d.blk_ptr[g + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int jc = 0; jc < ol; jc += 64) {
+        const int j = jc + lane;
+        const bool valid = j < ol;
+        A acc = 0;
+        int base = 0;
+        for (int b = b0; b < b1; ++b) {
+            const int nrb = d.b_nrows[b];
+            const int64_t stride = d.b_stride[b];
+            const VT *col = vals + d.b_val_off[b] + d.b_c0[b] + j;
+            const XT *xin = x + d.b_in[b];
+            int i = (wave - base) % NW;
+            if (i < 0) i += NW;
+            if (valid)
+                for (; i < nrb; i += NW) acc += (A)col[i * stride] * (A)xin[i];
+            base += nrb;
+        }
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && valid) {
+            A s = red[0][lane];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) s += red[w][lane];
+            y[ob + j] = (YT)((A)y[ob + j] + s);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_gather(const int32_t *__restrict__ perm, int64_t n, int nrhs,
+                         const double *__restrict__ x, int64_t ldx, double *__restrict__ xp)
+{
+    const int64_t tot = n * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, k = e % n;
+        xp[e] = x[perm[k] + c * ldx];
+    }
+}
+
+__global__ void k_scatter_add(const int32_t *__restrict__ perm, int64_t n, int nrhs, double alpha,
+                              const double *__restrict__ yp, double *__restrict__ y, int64_t ldy)
+{
+    const int64_t tot = n * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, k = e % n;
+        y[perm[k] + c * ldy] += alpha * yp[e];
+    }
+}
+
+template <typename T> __global__ void k_fill_zero(T *__restrict__ p, int64_t n)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = T(0);
+}
+
+}  // namespace
+
+// ===================================================================
+//  Launchers
+// ===================================================================
+
+void launch_near_assemble(h2b_kernel kernel, const RowPanels &rp, const int32_t *rperm,
+                          const int32_t *cperm, const GeoDev &geo, const QuadDev &quad,
+                          double *vals, hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    if (kernel == H2B_SLP)
+        hipLaunchKernelGGL(k_near_assemble<0>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, rperm,
+                           cperm, geo, quad, vals);
+    else
+        hipLaunchKernelGGL(k_near_assemble<1>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, rperm,
+                           cperm, geo, quad, vals);
+    hip_check(hipGetLastError(), "nearfield assembly launch");
+}
+
+template <typename T>
+void launch_leaf_basis(bool dlp_cols, const RowPanels &rp, const int32_t *perm, const double *axes,
+                       int m, const GeoDev &geo, const QuadDev &quad, T *vals, hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_leaf_basis<T>, dim3(rp.ngroups()), dim3(NT), 0, st, dlp_cols, rp.dev, perm,
+                       axes, m, geo, quad, vals);
+    hip_check(hipGetLastError(), "leaf basis launch");
+}
+
+template <typename T>
+void launch_transfer(const RowPanels &rp, const double *axes, int m, T *vals, hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_transfer<T>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, axes, m, vals);
+    hip_check(hipGetLastError(), "transfer launch");
+}
+
+template <typename T>
+void launch_coupling(const RowPanels &rp, const double *raxes, const double *caxes, int m, T *vals,
+                     hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_coupling<T>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, raxes, caxes, m, vals);
+    hip_check(hipGetLastError(), "coupling launch");
+}
+
+template <typename VT, typename XT, typename YT>
+void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
+                     bool accumulate, hipStream_t st)
+{
+    if (g1 <= g0) return;
+    using A = typename Acc<VT>::type;
+    const size_t shm = sizeof(A) * (CHUNK + (size_t)std::max(rp.max_nrows, 1));
+    hipLaunchKernelGGL((k_rowpanel<VT, XT, YT>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x,
+                       y, accumulate ? 1 : 0);
+    hip_check(hipGetLastError(), "row panel launch");
+}
+
+template <typename VT, typename XT, typename YT>
+void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
+                     hipStream_t st)
+{
+    if (g1 <= g0) return;
+    hipLaunchKernelGGL((k_colpanel<VT, XT, YT>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+    hip_check(hipGetLastError(), "column panel launch");
+}
+
+void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,
+                   double *xp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n * nrhs)), dim3(NT), 0, st, perm, n, nrhs, x, ldx, xp);
+    hip_check(hipGetLastError(), "gather launch");
+}
+
+void launch_scatter_add(const int32_t *perm, int64_t n, int nrhs, double alpha, const double *yp,
+                        double *y, int64_t ldy, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for(n * nrhs)), dim3(NT), 0, st, perm, n, nrhs, alpha,
+                       yp, y, ldy);
+    hip_check(hipGetLastError(), "scatter launch");
+}
+
+template <typename T> void launch_fill_zero(T *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(blocks_for(n)), dim3(NT), 0, st, p, n);
+    hip_check(hipGetLastError(), "fill launch");
+}
+
+// explicit instantiations
+template void launch_leaf_basis<double>(bool, const RowPanels &, const int32_t *, const double *, int,
+                                        const GeoDev &, const QuadDev &, double *, hipStream_t);
+template void launch_leaf_basis<float>(bool, const RowPanels &, const int32_t *, const double *, int,
+                                       const GeoDev &, const QuadDev &, float *, hipStream_t);
+template void launch_transfer<double>(const RowPanels &, const double *, int, double *, hipStream_t);
+template void launch_transfer<float>(const RowPanels &, const double *, int, float *, hipStream_t);
+template void launch_coupling<double>(const RowPanels &, const double *, const double *, int, double *,
+                                      hipStream_t);
+template void launch_coupling<float>(const RowPanels &, const double *, const double *, int, float *,
+                                     hipStream_t);
+template void launch_fill_zero<double>(double *, int64_t, hipStream_t);
+template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
+
+#define H2B_PANEL_INST(VT, XT, YT)                                                                      \
+    template void launch_rowpanel<VT, XT, YT>(const RowPanels &, int, int, const VT *, const XT *, YT *, \
+                                              bool, hipStream_t);                                       \
+    template void launch_colpanel<VT, XT, YT>(const ColPanels &, int, int, const VT *, const XT *, YT *, \
+                                              hipStream_t);
+H2B_PANEL_INST(double, double, double)
+H2B_PANEL_INST(float, double, float)
+H2B_PANEL_INST(float, float, float)
+H2B_PANEL_INST(float, float, double)
+#undef H2B_PANEL_INST
+
+}  // namespace h2b

@@ -1,0 +1,398 @@
+// Assembly of an H^2 operator (G or K) and the matrix-vector product driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+#include "device.hpp"
+#include "op.hpp"
+
+namespace h2b {
+
+// ------------------------------------------------------------- panels
+
+void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp)
+{
+    // output group per distinct input segment (keyed by its start), blocks in
+    // order of appearance
+    std::map<int, std::vector<int>> by_out;  // seg_in -> list of (group, segment)
+    std::map<int, int> out_len;
+    std::vector<std::pair<int, int>> refs;
+    for (int g = g0; g < g1; ++g)
+        for (int s = rp.seg_ptr[g]; s < rp.seg_ptr[g + 1]; ++s) {
+            by_out[rp.seg_in[s]].push_back((int)refs.size());
+            out_len[rp.seg_in[s]] = rp.seg_len[s];
+            refs.push_back({g, s});
+        }
+    // column offset of every segment inside its panel
+    std::vector<int> c0(rp.seg_in.size(), 0);
+    for (int g = g0; g < g1; ++g) {
+        int c = 0;
+        for (int s = rp.seg_ptr[g]; s < rp.seg_ptr[g + 1]; ++s) {
+            c0[s] = c;
+            c += rp.seg_len[s];
+        }
+    }
+    for (auto &kv : by_out) {
+        cp.out_begin.push_back(kv.first);
+        cp.out_len.push_back(out_len[kv.first]);
+        cp.max_out = std::max(cp.max_out, out_len[kv.first]);
+        for (int ref : kv.second) {
+            int g = refs[ref].first, s = refs[ref].second;
+            cp.b_val_off.push_back(rp.val_off[g]);
+            cp.b_stride.push_back(rp.ncols[g]);
+            cp.b_c0.push_back(c0[s]);
+            cp.b_nrows.push_back(rp.nrows[g]);
+            cp.b_in.push_back(rp.out_begin[g]);
+        }
+        cp.blk_ptr.push_back((int32_t)cp.b_in.size());
+    }
+}
+
+// -------------------------------------------------------------- bases
+
+static int basis_quad_order(int m) { return (3 * m) / 2 + 1; }
+
+static QuadDev make_quad(int q)
+{
+    if (q < 1 || q > QMAX) fail(H2B_EINVAL, "quadrature order out of range");
+    QuadDev Q{};
+    std::vector<double> t, w;
+    gauss_legendre_unit(q, t, w);
+    Q.q = q;
+    for (int i = 0; i < q; ++i) {
+        Q.t[i] = t[i];
+        Q.w[i] = w[i];
+    }
+    return Q;
+}
+
+// Structure of a cluster basis with uniform rank k on every cluster.
+static void build_basis_structure(Basis &B, int k)
+{
+    const Tree &T = *B.tree;
+    const int64_t nc = T.nclusters();
+    B.rank.assign(nc, k);
+    B.hat_off.resize(nc + 1);
+    B.hat_off[0] = 0;
+    for (int64_t c = 0; c < nc; ++c) B.hat_off[c + 1] = B.hat_off[c] + B.rank[c];
+    B.hat_total = B.hat_off[nc];
+    if (B.hat_total > INT32_MAX) fail(H2B_ENOTSUP, "too many cluster coefficients for 32-bit offsets");
+    // leaves: V_t^T, k x |t|
+    for (int c : T.leaves) {
+        B.leaf.begin_group(c, (int)B.hat_off[c], B.rank[c]);
+        B.leaf.add_segment(T.begin[c], T.size(c), c);
+        B.leaf.end_group();
+    }
+    transpose_panels(B.leaf, 0, B.leaf.ngroups(), B.leaf_T);
+    // transfers, deepest parents first
+    B.fw_steps.clear();
+    for (int lev = T.nlevels - 2; lev >= 0; --lev) {
+        int g0 = B.trans.ngroups();
+        for (int c : T.by_level[lev]) {
+            if (T.nchild[c] == 0) continue;
+            B.trans.begin_group(c, (int)B.hat_off[c], B.rank[c]);
+            for (int ch : {T.child0[c], T.child1[c]})
+                B.trans.add_segment((int)B.hat_off[ch], B.rank[ch], ch);
+            B.trans.end_group();
+        }
+        B.fw_steps.push_back({g0, B.trans.ngroups()});
+    }
+    // backward: top level first; transposed panels of each step
+    B.bw_steps.clear();
+    for (auto it = B.fw_steps.rbegin(); it != B.fw_steps.rend(); ++it) {
+        int o0 = B.trans_T.ngroups();
+        transpose_panels(B.trans, it->first, it->second, B.trans_T);
+        B.bw_steps.push_back({o0, B.trans_T.ngroups()});
+    }
+}
+
+template <typename T>
+static void assemble_basis(Basis &B, int m, const DevMem &axes, const GeoDev &geo, hipStream_t st)
+{
+    B.leaf_vals.alloc(sizeof(T) * std::max<int64_t>(B.leaf.total, 1));
+    B.trans_vals.alloc(sizeof(T) * std::max<int64_t>(B.trans.total, 1));
+    QuadDev Q = make_quad(basis_quad_order(m));
+    launch_leaf_basis<T>(B.dlp_cols, B.leaf, B.perm_dev, axes.as<double>(), m, geo, Q,
+                         B.leaf_vals.as<T>(), st);
+    launch_transfer<T>(B.trans, axes.as<double>(), m, B.trans_vals.as<T>(), st);
+}
+
+// ---------------------------------------------------------- operator
+
+Op::~Op()
+{
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+static void upload_tree(Basis &B, hipStream_t st)
+{
+    Packer pk;
+    pk.add(B.tree->perm, const_cast<int32_t **>(&B.perm_dev));
+    pk.upload(B.perm_mem, st);
+}
+
+static void upload_axes(const Tree &T, int m, DevMem &mem, hipStream_t st)
+{
+    std::vector<double> ax((size_t)T.nclusters() * 3 * m);
+    for (int64_t c = 0; c < T.nclusters(); ++c) cheb_axes(T, (int)c, m, &ax[(size_t)c * 3 * m]);
+    mem.alloc(ax.size() * sizeof(double));
+    hip_check(hipMemcpyAsync(mem.p, ax.data(), ax.size() * sizeof(double), hipMemcpyHostToDevice, st),
+              "axes upload");
+    hip_check(hipStreamSynchronize(st), "axes upload");
+}
+
+std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
+                                const h2b_params &p, hipStream_t st)
+{
+    if (p.order_m < 1 || p.order_m > MMAX) fail(H2B_EINVAL, "order_m must be in 1..6");
+    if (p.q_near < 2 || p.q_near > QMAX) fail(H2B_EINVAL, "q_near must be in 2..16");
+    if (p.farfield_dtype != H2B_F64 && p.farfield_dtype != H2B_F32)
+        fail(H2B_EINVAL, "farfield_dtype must be H2B_F64 or H2B_F32");
+    if (!(p.recompress_tol >= 0.0)) fail(H2B_EINVAL, "recompress_tol must be >= 0");
+    if (kernel == H2B_SLP && blocks->cols->space != H2B_P0)
+        fail(H2B_EINVAL, "the single-layer matrix needs a P0 column tree");
+    if (kernel == H2B_DLP && blocks->cols->space != H2B_P1)
+        fail(H2B_EINVAL, "the double-layer matrix needs a P1 column tree");
+    if (kernel != H2B_SLP && kernel != H2B_DLP) fail(H2B_EINVAL, "unknown kernel");
+    if (p.recompress_tol > 0.0) fail(H2B_ENOTSUP, "recompression is not available in this build");
+
+    auto op = std::make_unique<Op>();
+    op->blocks = blocks;
+    op->kernel = kernel;
+    op->params = p;
+    const Tree &R = *blocks->rows, &C = *blocks->cols;
+    const Mesh &M = *R.mesh;
+    op->nrows = R.n;
+    op->ncols = C.n;
+    const int m = p.order_m;
+    const int k = m * m * m;
+
+    // geometry
+    {
+        Packer pk;
+        pk.add(M.vx, const_cast<double **>(&op->geo.vx));
+        pk.add(M.vy, const_cast<double **>(&op->geo.vy));
+        pk.add(M.vz, const_cast<double **>(&op->geo.vz));
+        pk.add(M.t0, const_cast<int32_t **>(&op->geo.t0));
+        pk.add(M.t1, const_cast<int32_t **>(&op->geo.t1));
+        pk.add(M.t2, const_cast<int32_t **>(&op->geo.t2));
+        pk.add(M.nx, const_cast<double **>(&op->geo.nx));
+        pk.add(M.ny, const_cast<double **>(&op->geo.ny));
+        pk.add(M.nz, const_cast<double **>(&op->geo.nz));
+        pk.add(M.vt_ptr, const_cast<int64_t **>(&op->geo.vt_ptr));
+        pk.add(M.vt_idx, const_cast<int32_t **>(&op->geo.vt_idx));
+        pk.upload(op->geo_mem, st);
+    }
+
+    // bases
+    op->rowb = std::make_shared<Basis>();
+    op->rowb->tree = blocks->rows;
+    op->rowb->dlp_cols = false;
+    upload_tree(*op->rowb, st);
+    if (kernel == H2B_SLP) {
+        op->colb = op->rowb;
+    } else {
+        op->colb = std::make_shared<Basis>();
+        op->colb->tree = blocks->cols;
+        op->colb->dlp_cols = true;
+        upload_tree(*op->colb, st);
+    }
+    upload_axes(R, m, op->rowb->axes, st);
+    if (op->colb != op->rowb) upload_axes(C, m, op->colb->axes, st);
+    std::vector<Basis *> bases{op->rowb.get()};
+    if (op->colb != op->rowb) bases.push_back(op->colb.get());
+    for (Basis *B : bases) {
+        build_basis_structure(*B, k);
+        B->leaf.upload(st);
+        B->leaf_T.upload(st);
+        B->trans.upload(st);
+        B->trans_T.upload(st);
+    }
+
+    // nearfield panels (rows grouped by row leaf, blocks in construction order)
+    {
+        std::vector<std::vector<int>> per_row(R.nclusters());
+        for (size_t b = 0; b < blocks->near_t.size(); ++b) per_row[blocks->near_t[b]].push_back((int)b);
+        for (int t : R.leaves) {
+            if (per_row[t].empty()) continue;
+            op->near.begin_group(t, R.begin[t], R.size(t));
+            for (int b : per_row[t]) {
+                int s = blocks->near_s[b];
+                op->near.add_segment(C.begin[s], C.size(s), s);
+            }
+            op->near.end_group();
+        }
+        transpose_panels(op->near, 0, op->near.ngroups(), op->near_T);
+        op->near.upload(st);
+        op->near_T.upload(st);
+    }
+    // coupling panels (grouped by row cluster)
+    {
+        std::vector<std::vector<int>> per_row(R.nclusters());
+        for (size_t b = 0; b < blocks->far_t.size(); ++b) per_row[blocks->far_t[b]].push_back((int)b);
+        for (int64_t t = 0; t < R.nclusters(); ++t) {
+            if (per_row[t].empty()) continue;
+            op->cpl.begin_group((int)t, (int)op->rowb->hat_off[t], op->rowb->rank[t]);
+            for (int b : per_row[t]) {
+                int s = blocks->far_s[b];
+                op->cpl.add_segment((int)op->colb->hat_off[s], op->colb->rank[s], s);
+            }
+            op->cpl.end_group();
+        }
+        transpose_panels(op->cpl, 0, op->cpl.ngroups(), op->cpl_T);
+        op->cpl.upload(st);
+        op->cpl_T.upload(st);
+    }
+
+    // values
+    op->near_vals.alloc(sizeof(double) * std::max<int64_t>(op->near.total, 1));
+    QuadDev Qn = make_quad(p.q_near);
+    launch_near_assemble(kernel, op->near, op->rowb->perm_dev, op->colb->perm_dev, op->geo, Qn,
+                         op->near_vals.as<double>(), st);
+    const size_t fsz = (p.farfield_dtype == H2B_F64) ? sizeof(double) : sizeof(float);
+    op->cpl_vals.alloc(fsz * std::max<int64_t>(op->cpl.total, 1));
+    for (Basis *B : bases) {
+        if (p.farfield_dtype == H2B_F64)
+            assemble_basis<double>(*B, m, B->axes, op->geo, st);
+        else
+            assemble_basis<float>(*B, m, B->axes, op->geo, st);
+    }
+    if (p.farfield_dtype == H2B_F64)
+        launch_coupling<double>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
+                                op->cpl_vals.as<double>(), st);
+    else
+        launch_coupling<float>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
+                               op->cpl_vals.as<float>(), st);
+    hip_check(hipStreamSynchronize(st), "assembly");
+
+    // work vectors
+    const int64_t nmax = std::max(op->nrows, op->ncols);
+    const int64_t hmax = std::max(op->rowb->hat_total, op->colb->hat_total);
+    op->xp.alloc(sizeof(double) * nmax);
+    op->yp.alloc(sizeof(double) * nmax);
+    op->xhat.alloc(fsz * std::max<int64_t>(hmax, 1));
+    op->yhat.alloc(fsz * std::max<int64_t>(hmax, 1));
+    for (auto &e : op->ev) hip_check(hipEventCreate(&e), "event create");
+    return op;
+}
+
+// --------------------------------------------------------------- product
+
+template <typename F>
+static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
+{
+    launch_rowpanel<F, double, F>(B.leaf, 0, B.leaf.ngroups(), B.leaf_vals.as<F>(), xp, xhat, false, st);
+    for (auto &s : B.fw_steps)
+        launch_rowpanel<F, F, F>(B.trans, s.first, s.second, B.trans_vals.as<F>(), xhat, xhat, false, st);
+}
+
+template <typename F>
+static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
+{
+    for (auto &s : B.bw_steps)
+        launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), yhat, yhat, st);
+    launch_colpanel<F, F, double>(B.leaf_T, 0, B.leaf_T.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st);
+}
+
+template <typename F>
+static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
+{
+    const Basis &Bin = trans ? *op.rowb : *op.colb;
+    const Basis &Bout = trans ? *op.colb : *op.rowb;
+    const int64_t nin = trans ? op.nrows : op.ncols;
+    const int64_t nout = trans ? op.ncols : op.nrows;
+    double *xp = op.xp.as<double>(), *yp = op.yp.as<double>();
+    F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
+    const bool tm = op.timing;
+    if (tm) hip_check(hipEventRecord(op.ev[0], st), "event");
+    launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
+    if (tm) hip_check(hipEventRecord(op.ev[1], st), "event");
+    forward<F>(Bin, xp, xhat, st);
+    if (tm) hip_check(hipEventRecord(op.ev[2], st), "event");
+    launch_fill_zero<F>(yhat, Bout.hat_total, st);
+    launch_fill_zero<double>(yp, nout, st);
+    if (!trans)
+        launch_rowpanel<F, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, true, st);
+    else
+        launch_colpanel<F, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, st);
+    if (tm) hip_check(hipEventRecord(op.ev[3], st), "event");
+    backward<F>(Bout, yhat, yp, st);
+    if (tm) hip_check(hipEventRecord(op.ev[4], st), "event");
+    if (!trans)
+        launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
+                                                xp, yp, true, st);
+    else
+        launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
+                                                op.near_vals.as<double>(), xp, yp, st);
+    if (tm) hip_check(hipEventRecord(op.ev[5], st), "event");
+    launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, y, nout, st);
+    if (tm) hip_check(hipEventRecord(op.ev[6], st), "event");
+}
+
+void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+            int nrhs, hipStream_t st)
+{
+    const int64_t nin = trans ? op.nrows : op.ncols;
+    const int64_t nout = trans ? op.ncols : op.nrows;
+    if (!x || !y) fail(H2B_EINVAL, "x and y must not be NULL");
+    if (nrhs < 1 || nrhs > 64) fail(H2B_EINVAL, "nrhs must be in 1..64");
+    if (ldx < nin || ldy < nout) fail(H2B_EINVAL, "leading dimension smaller than the vector length");
+    {
+        const char *xb = reinterpret_cast<const char *>(x);
+        const char *yb = reinterpret_cast<const char *>(y);
+        const char *xe = xb + sizeof(double) * (size_t)(ldx * (nrhs - 1) + nin);
+        const char *ye = yb + sizeof(double) * (size_t)(ldy * (nrhs - 1) + nout);
+        if (xb < ye && yb < xe) fail(H2B_EINVAL, "x and y overlap");
+    }
+    for (int c = 0; c < nrhs; ++c) {
+        if (op.params.farfield_dtype == H2B_F64)
+            product_one<double>(op, trans, alpha, x + c * ldx, y + c * ldy, st);
+        else
+            product_one<float>(op, trans, alpha, x + c * ldx, y + c * ldy, st);
+    }
+    op.timed_valid = op.timing;
+}
+
+void phase_times(Op &op, double out[6])
+{
+    if (!op.timed_valid) fail(H2B_ESTATE, "no timed product recorded (enable timing first)");
+    hip_check(hipEventSynchronize(op.ev[6]), "event sync");
+    for (int i = 0; i < 6; ++i) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, op.ev[i], op.ev[i + 1]), "event time");
+        out[i] = ms;
+    }
+}
+
+void op_stats(const Op &op, h2b_op_stats &s)
+{
+    s = h2b_op_stats{};
+    s.rows = op.nrows;
+    s.cols = op.ncols;
+    s.nfar = (int64_t)op.blocks->far_t.size();
+    s.nnear = (int64_t)op.blocks->near_t.size();
+    s.near_entries = op.near.total;
+    s.coupling_entries = op.cpl.total;
+    s.row_basis_entries = op.rowb->leaf.total + op.rowb->trans.total;
+    s.col_basis_entries = (op.colb == op.rowb) ? 0 : op.colb->leaf.total + op.colb->trans.total;
+    const int64_t fsz = (op.params.farfield_dtype == H2B_F64) ? 8 : 4;
+    s.bytes_near = op.near.total * 8;
+    s.bytes_far = (s.coupling_entries + s.row_basis_entries + s.col_basis_entries) * fsz;
+    s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.xhat.bytes + op.yhat.bytes);
+    auto rk = [](const Basis &B, int32_t &mx, double &mean) {
+        mx = 0;
+        double sum = 0;
+        for (int r : B.rank) {
+            mx = std::max(mx, r);
+            sum += r;
+        }
+        mean = B.rank.empty() ? 0.0 : sum / B.rank.size();
+    };
+    rk(*op.rowb, s.max_rank_row, s.mean_rank_row);
+    rk(*op.colb, s.max_rank_col, s.mean_rank_col);
+}
+
+}  // namespace h2b

@@ -1,0 +1,62 @@
+// Assembled H^2 operator and its product driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <utility>
+#include <vector>
+
+#include "device.hpp"
+
+namespace h2b {
+
+// Cluster basis on one tree: leaf matrices (stored transposed) and transfer
+// matrices, each with the panel descriptors of the forward (rows) and the
+// backward (transposed) products.
+struct Basis {
+    std::shared_ptr<const Tree> tree;
+    bool dlp_cols = false;                  // normal-derivative basis of the P1 space
+    std::vector<int32_t> rank;              // k_t per cluster
+    std::vector<int64_t> hat_off;           // offset of cluster coefficients
+    int64_t hat_total = 0;
+    RowPanels leaf;                         // V_t^T per leaf
+    ColPanels leaf_T;
+    RowPanels trans;                        // [E_c0^T | E_c1^T] per parent, deepest level first
+    ColPanels trans_T;
+    std::vector<std::pair<int, int>> fw_steps;  // group ranges of trans, bottom-up
+    std::vector<std::pair<int, int>> bw_steps;  // group ranges of trans_T, top-down
+    DevMem leaf_vals, trans_vals;
+    DevMem axes;                            // Chebyshev points, 3*m per cluster
+    DevMem perm_mem;
+    const int32_t *perm_dev = nullptr;
+};
+
+struct Op {
+    std::shared_ptr<const Blocks> blocks;
+    h2b_kernel kernel = H2B_SLP;
+    h2b_params params{};
+    int64_t nrows = 0, ncols = 0;
+    std::shared_ptr<Basis> rowb, colb;      // colb == rowb for G
+    GeoDev geo{};
+    DevMem geo_mem;
+    RowPanels near;
+    ColPanels near_T;
+    DevMem near_vals;
+    RowPanels cpl;
+    ColPanels cpl_T;
+    DevMem cpl_vals;
+    DevMem xp, yp, xhat, yhat;              // product work vectors
+    bool timing = false, timed_valid = false;
+    hipEvent_t ev[7] = {};
+    ~Op();
+};
+
+std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
+                                const h2b_params &p, hipStream_t st);
+void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+            int nrhs, hipStream_t st);
+void phase_times(Op &op, double out[6]);
+void op_stats(const Op &op, h2b_op_stats &s);
+
+}  // namespace h2b

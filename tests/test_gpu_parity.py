@@ -1,0 +1,174 @@
+"""GPU parity: the HIP H^2 products against the CPU oracle, element by element.
+
+* Far field disabled (every entry from the near-field quadrature): the GPU
+  product equals the oracle's dense Galerkin matrix times x to rounding
+  (bound 1e-10 relative to max|y|).
+* Far field enabled: the GPU product equals the oracle's dense H^2 matrix
+  (same trees, same interpolation, written out without transfer matrices) to
+  rounding, and differs from the dense Galerkin matrix by the interpolation
+  error of the order m.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import h2
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _lib():
+    import paper_2001_05523_amd as h
+    return h
+
+
+def _run(op, x, trans=False, alpha=1.0, y0=None):
+    torch = _torch()
+    nout = op.shape[1] if trans else op.shape[0]
+    X = torch.tensor(x, dtype=torch.float64, device="cuda")
+    Y = (torch.zeros(nout, dtype=torch.float64, device="cuda") if y0 is None
+         else torch.tensor(y0, dtype=torch.float64, device="cuda"))
+    op.matvec(X, Y, alpha=alpha, trans=trans)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()
+
+
+def _maxrel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+_dense_cache = {}
+
+
+def _dense(s, kernel, q):
+    key = (s, kernel, q)
+    if key not in _dense_cache:
+        v, t = synth.octa_sphere(s)
+        _dense_cache[key] = (oracle.slp_dense if kernel == "slp" else oracle.dlp_dense)(v, t, q)
+    return _dense_cache[key]
+
+
+@pytest.mark.parametrize("s,leaf", [(2, 8), (4, 8), (8, 32), (8, 13)])
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+@pytest.mark.parametrize("trans", [False, True])
+def test_dense_parity_far_disabled(s, leaf, kernel, trans):
+    """H^2 disabled: every entry is a near-field quadrature value, so the GPU
+    product must equal the oracle's dense matrix to rounding (<= 1e-10)."""
+    h = _lib()
+    v, t = synth.octa_sphere(s)
+    q = 4
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, q_near=q, far_disabled=True)
+    A = _dense(s, kernel, q)
+    nin = A.shape[0] if trans else A.shape[1]
+    x = synth.random_vector(nin, 101)
+    y0 = synth.random_vector(A.shape[1] if trans else A.shape[0], 7)
+    y = _run(op, x, trans=trans, alpha=-0.7, y0=y0)
+    ref = y0 - 0.7 * ((A.T if trans else A) @ x)
+    assert _maxrel(y, ref) <= 1e-10
+
+
+def test_dense_parity_q6():
+    h = _lib()
+    v, t = synth.octa_sphere(4)
+    op = h.Operator(v, t, kernel="dlp", leaf=16, q_near=6, far_disabled=True)
+    K = oracle.dlp_dense(v, t, 6)
+    x = synth.random_vector(len(v), 3)
+    assert _maxrel(_run(op, x), K @ x) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel,s,leaf,m", [("slp", 8, 32, 3), ("slp", 8, 16, 2), ("slp", 16, 32, 4),
+                                             ("dlp", 16, 16, 3), ("dlp", 16, 32, 4)])
+def test_h2_parity_against_oracle_h2(kernel, s, leaf, m):
+    """Interpolation far field: equal to the oracle's dense H^2 matrix to
+    rounding; the error against the dense Galerkin matrix is the interpolation
+    error of order m."""
+    h = _lib()
+    v, t = synth.octa_sphere(s)
+    q = 4
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=m, q_near=q)
+    assert op.blocks.nfar > 0
+    A = _dense(s, kernel, q)
+    H, _ = h2.h2_dense(v, t, kernel, leaf, m, near_matrix=A)
+    for trans in (False, True):
+        nin = A.shape[0] if trans else A.shape[1]
+        x = synth.random_vector(nin, 101 + trans)
+        y = _run(op, x, trans=trans)
+        Hx = (H.T if trans else H) @ x
+        Ax = (A.T if trans else A) @ x
+        assert _maxrel(y, Hx) <= 1e-11
+        err = np.linalg.norm(y - Ax) / np.linalg.norm(Ax)
+        err_oracle = np.linalg.norm(Hx - Ax) / np.linalg.norm(Ax)
+        print("%s m=%d trans=%d interpolation error %.3e (oracle H2 %.3e)"
+              % (kernel, m, trans, err, err_oracle))
+        assert abs(err - err_oracle) <= 1e-3 * err_oracle + 1e-12
+        assert err_oracle < 1e-2
+
+
+def test_mixed_precision_far_field():
+    """FP32 bases and coupling matrices with FP32 accumulation; near field FP64.
+    Relative difference to the FP64 product <= 1e-5."""
+    h = _lib()
+    v, t = synth.octa_sphere(16)
+    for kernel in ("slp", "dlp"):
+        op64 = h.Operator(v, t, kernel=kernel, leaf=16, order_m=4, q_near=4)
+        op32 = h.Operator(v, t, kernel=kernel, leaf=16, order_m=4, q_near=4, farfield_dtype="f32")
+        for trans in (False, True):
+            nin = op64.shape[0] if trans else op64.shape[1]
+            x = synth.random_vector(nin, 11)
+            y64 = _run(op64, x, trans=trans)
+            y32 = _run(op32, x, trans=trans)
+            assert np.linalg.norm(y32 - y64) / np.linalg.norm(y64) <= 1e-5
+
+
+def test_multiple_right_hand_sides():
+    torch = _torch()
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    op = h.Operator(v, t, kernel="dlp", leaf=16, order_m=3, q_near=4)
+    nr, nc = op.shape
+    X = torch.tensor(synth.random_vector(nc + 5, 5, cols=3), device="cuda")[:nc]
+    Y = torch.zeros((nr + 3, 3), dtype=torch.float64, device="cuda").t().contiguous().t()[:nr]
+    op.matvec(X, Y, alpha=2.0)
+    torch.cuda.synchronize()
+    for c in range(3):
+        y1 = _run(op, X[:, c].cpu().numpy(), alpha=2.0)
+        np.testing.assert_array_equal(Y[:, c].cpu().numpy(), y1)
+
+
+def test_argument_errors_leave_y_untouched():
+    torch = _torch()
+    h = _lib()
+    v, t = synth.octa_sphere(4)
+    op = h.Operator(v, t, kernel="slp", leaf=8, order_m=2)
+    x = torch.ones(len(t), dtype=torch.float64, device="cuda")
+    y = torch.full((len(t),), 3.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(h.H2BError):
+        h._check(h.h2b_matvec(op.handle, 0, 1.0, h._vp(x.data_ptr()), len(t) - 1,
+                              h._vp(y.data_ptr()), len(t), 1, None))
+    with pytest.raises(h.H2BError):
+        h._check(h.h2b_matvec(op.handle, 0, 1.0, h._vp(x.data_ptr()), len(t),
+                              h._vp(x.data_ptr()), len(t), 1, None))
+    torch.cuda.synchronize()
+    assert torch.all(y == 3.0)
+    with pytest.raises(h.H2BError):
+        h.Operator(v, t, kernel="slp", leaf=8, order_m=9)
+    with pytest.raises(h.H2BError):
+        h.Operator(v, t, kernel="slp", leaf=8, q_near=1)
+
+
+def test_single_hip_runtime_loaded():
+    """The library and torch share one HIP runtime in the process."""
+    torch = _torch()
+    _lib()
+    torch.zeros(1, device="cuda")
+    maps = open("/proc/self/maps").read().splitlines()
+    libs = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(libs) == 1, libs
+    assert any("libh2bem.so" in ln for ln in maps)

@@ -1,0 +1,129 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every declared
+symbol is exported, the trees and block lists equal the oracle's (integer and
+index work, bit-exact), and invalid input is rejected before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import h2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2001_05523_amd as h
+    return h
+
+
+def test_header_symbols_exported():
+    h = _lib()
+    text = open(os.path.join(ROOT, "include", "h2bem.h")).read()
+    decl = set(re.findall(r"\b(h2b_[a-z_0-9]+)\s*\(", text))
+    assert decl, "no declarations found"
+    for name in decl:
+        assert hasattr(h._lib, name), name
+    assert decl == set(h.EXPORTED)
+
+
+@pytest.mark.parametrize("space,leaf,s", [(0, 32, 8), (1, 16, 8), (0, 8, 4), (1, 5, 4), (0, 64, 16)])
+def test_cluster_tree_equals_oracle(space, leaf, s):
+    h = _lib()
+    v, t = synth.octa_sphere(s)
+    T = h.Tree(h.Mesh(v, t), space, leaf)
+    a = T.arrays()
+    pts = v[t].mean(axis=1) if space == 0 else v
+    _, perm, cl = h2.cluster_tree(pts, leaf)
+    h2.support_boxes(cl, v, t, "P0" if space == 0 else "P1")
+    assert T.nclusters == len(cl)
+    np.testing.assert_array_equal(a["perm"], perm)
+    np.testing.assert_array_equal(a["begin"], [c.begin for c in cl])
+    np.testing.assert_array_equal(a["end"], [c.end for c in cl])
+    np.testing.assert_array_equal(a["box"], np.array([np.r_[c.lo, c.hi] for c in cl]))
+
+
+@pytest.mark.parametrize("kernel,leaf,s", [("slp", 32, 8), ("slp", 16, 16), ("dlp", 16, 16),
+                                           ("dlp", 8, 8)])
+def test_block_lists_equal_oracle(kernel, leaf, s):
+    h = _lib()
+    v, t = synth.octa_sphere(s)
+    m = h.Mesh(v, t)
+    R = h.Tree(m, 0, leaf)
+    C = R if kernel == "slp" else h.Tree(m, 1, leaf)
+    B = h.Blocks(R, C, 1.0)
+    far, near = B.lists()
+    _, _, rcl = h2.cluster_tree(v[t].mean(axis=1), leaf)
+    h2.support_boxes(rcl, v, t, "P0")
+    if kernel == "slp":
+        ccl = rcl
+    else:
+        _, _, ccl = h2.cluster_tree(v, leaf)
+        h2.support_boxes(ccl, v, t, "P1")
+    f, n = h2.block_tree(rcl[0], ccl[0], 1.0)
+    np.testing.assert_array_equal(far.reshape(-1, 2), np.array([(a.id, b.id) for a, b in f]).reshape(-1, 2))
+    np.testing.assert_array_equal(near, np.array([(a.id, b.id) for a, b in n]))
+    ne = sum((a.end - a.begin) * (b.end - b.begin) for a, b in n)
+    assert B.near_entries == ne
+
+
+def test_far_disabled_gives_only_near_blocks():
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    m = h.Mesh(v, t)
+    R = h.Tree(m, 0, 32)
+    B = h.Blocks(R, R, 1.0, far_disabled=True)
+    assert B.nfar == 0
+    assert B.near_entries == len(t) ** 2
+
+
+def test_invalid_meshes_rejected():
+    h = _lib()
+    v, t = synth.octa_sphere(2)
+    bad = t.copy()
+    bad[3, 1] = len(v)
+    with pytest.raises(h.H2BError) as e:
+        h.Mesh(v, bad)
+    assert e.value.code == h.H2B_EINVAL and "out of range" in str(e.value)
+    bad = t.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(h.H2BError):
+        h.Mesh(v, bad)
+    vv = v.copy()
+    vv[t[2, 2]] = vv[t[2, 0]]
+    with pytest.raises(h.H2BError) as e:
+        h.Mesh(vv, t)
+    assert "zero area" in str(e.value)
+    vv = v.copy()
+    vv[0, 0] = np.nan
+    with pytest.raises(h.H2BError):
+        h.Mesh(vv, t)
+
+
+def test_invalid_tree_and_block_arguments():
+    h = _lib()
+    v, t = synth.octa_sphere(2)
+    m = h.Mesh(v, t)
+    with pytest.raises(h.H2BError):
+        h.Tree(m, 0, 0)
+    with pytest.raises(h.H2BError):
+        h.Tree(m, 7, 4)
+    R = h.Tree(m, 0, 4)
+    C = h.Tree(m, 1, 4)
+    with pytest.raises(h.H2BError):
+        h.Blocks(R, C, 0.0)
+    with pytest.raises(h.H2BError):
+        h.Blocks(C, R, 1.0)  # rows must be the triangle tree
+    other = h.Tree(h.Mesh(v, t), 0, 4)
+    with pytest.raises(h.H2BError):
+        h.Blocks(R, other, 1.0)
+
+
+def test_null_arguments_rejected():
+    h = _lib()
+    out = ctypes.c_void_p()
+    assert h.h2b_tree_build(None, 0, 4, ctypes.byref(out)) == h.H2B_EINVAL
+    assert b"NULL" in h.h2b_last_error()
+    assert h.h2b_matvec(None, 0, 1.0, None, 1, None, 1, 1, None) == h.H2B_EINVAL
