@@ -133,7 +133,7 @@ h2b_status h2b_blocks_lists(h2b_blocks blocks, int32_t *far_pairs, int32_t *near
 
 typedef struct {
     int order_m;            /* Chebyshev points per axis, k = m^3 per cluster; 1..6 */
-    int q_near;             /* Gauss points per dimension of the near-field quadrature; 1..16 */
+    int q_near;             /* Gauss points per dimension of the near-field quadrature; 2..16 */
     double recompress_tol;  /* > 0: algebraic recompression of the cluster bases to this
                                relative tolerance; 0: plain interpolation */
     h2b_dtype farfield_dtype; /* storage/arithmetic of bases and coupling matrices */
@@ -166,6 +166,7 @@ typedef struct {
     int64_t col_basis_entries;     /* same, column tree (0 if shared with rows) */
     int64_t bytes_near, bytes_far; /* device bytes of nearfield and farfield data */
     int64_t bytes_vectors;         /* device bytes of the product's work vectors */
+    int64_t row_coeffs, col_coeffs; /* cluster coefficients (sum of ranks), row / column tree */
     int32_t max_rank_row, max_rank_col;
     double mean_rank_row, mean_rank_col;
 } h2b_op_stats;
@@ -186,10 +187,14 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
 h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
 
-/* Per-phase timing of the most recent h2b_matvec on an operator, in
- * milliseconds, measured with HIP events on the product's own stream when
- * timing was enabled by h2b_op_set_timing(op, 1).  phases[0..5] = gather,
- * forward, coupling, backward, nearfield, scatter.  Waits for the events. */
+/* Per-phase timing of the products on an operator, measured with HIP events on
+ * each product's own stream.  h2b_op_set_timing(op, 1) starts recording (one
+ * event set per single-vector product, created on the host as needed);
+ * h2b_op_phase_times waits for the last recorded product and returns the mean
+ * milliseconds per product of phases[0..5] = gather, forward transformation,
+ * coupling, backward transformation, nearfield, scatter, then restarts the
+ * average.  The coupling and nearfield phases each contain exactly one kernel
+ * launch.  Errors: H2B_ESTATE if nothing was recorded. */
 h2b_status h2b_op_set_timing(h2b_op op, int enable);
 h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[6]);
 

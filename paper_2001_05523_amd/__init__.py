@@ -46,6 +46,7 @@ class h2b_op_stats(ctypes.Structure):
                 ("near_entries", _i64), ("coupling_entries", _i64),
                 ("row_basis_entries", _i64), ("col_basis_entries", _i64),
                 ("bytes_near", _i64), ("bytes_far", _i64), ("bytes_vectors", _i64),
+                ("row_coeffs", _i64), ("col_coeffs", _i64),
                 ("max_rank_row", _i32), ("max_rank_col", _i32),
                 ("mean_rank_row", _dbl), ("mean_rank_col", _dbl)]
 

@@ -221,7 +221,7 @@ h2b_status h2b_op_set_timing(h2b_op op, int enable)
     return guarded([&] {
         need(op, "op");
         op->op->timing = enable != 0;
-        op->op->timed_valid = false;
+        op->op->nev = 0;
     });
 }
 

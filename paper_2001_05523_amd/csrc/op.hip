@@ -123,8 +123,9 @@ static void assemble_basis(Basis &B, int m, const DevMem &axes, const GeoDev &ge
 
 Op::~Op()
 {
-    for (auto &e : ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &set : ev)
+        for (auto &e : set)
+            if (e) (void)hipEventDestroy(e);
 }
 
 static void upload_tree(Basis &B, hipStream_t st)
@@ -275,7 +276,6 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     op->yp.alloc(sizeof(double) * nmax);
     op->xhat.alloc(fsz * std::max<int64_t>(hmax, 1));
     op->yhat.alloc(fsz * std::max<int64_t>(hmax, 1));
-    for (auto &e : op->ev) hip_check(hipEventCreate(&e), "event create");
     return op;
 }
 
@@ -297,6 +297,9 @@ static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
     launch_colpanel<F, F, double>(B.leaf_T, 0, B.leaf_T.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st);
 }
 
+// Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
+// [4] after backward, [5] after nearfield, [6] after scatter.  The coupling and
+// nearfield phases each bracket exactly one kernel launch.
 template <typename F>
 static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
 {
@@ -306,30 +309,41 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     const int64_t nout = trans ? op.ncols : op.nrows;
     double *xp = op.xp.as<double>(), *yp = op.yp.as<double>();
     F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
-    const bool tm = op.timing;
-    if (tm) hip_check(hipEventRecord(op.ev[0], st), "event");
-    launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
-    if (tm) hip_check(hipEventRecord(op.ev[1], st), "event");
-    forward<F>(Bin, xp, xhat, st);
-    if (tm) hip_check(hipEventRecord(op.ev[2], st), "event");
+    hipEvent_t *ev = nullptr;
+    if (op.timing) {
+        if (op.nev == op.ev.size()) {
+            std::array<hipEvent_t, 7> set{};
+            for (auto &e : set) hip_check(hipEventCreate(&e), "event create");
+            op.ev.push_back(set);
+        }
+        ev = op.ev[op.nev++].data();
+    }
+    auto mark = [&](int i) {
+        if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
+    };
     launch_fill_zero<F>(yhat, Bout.hat_total, st);
     launch_fill_zero<double>(yp, nout, st);
+    mark(0);
+    launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
+    mark(1);
+    forward<F>(Bin, xp, xhat, st);
+    mark(2);
     if (!trans)
         launch_rowpanel<F, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, true, st);
     else
         launch_colpanel<F, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, st);
-    if (tm) hip_check(hipEventRecord(op.ev[3], st), "event");
+    mark(3);
     backward<F>(Bout, yhat, yp, st);
-    if (tm) hip_check(hipEventRecord(op.ev[4], st), "event");
+    mark(4);
     if (!trans)
         launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
                                                 xp, yp, true, st);
     else
         launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
                                                 op.near_vals.as<double>(), xp, yp, st);
-    if (tm) hip_check(hipEventRecord(op.ev[5], st), "event");
+    mark(5);
     launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, y, nout, st);
-    if (tm) hip_check(hipEventRecord(op.ev[6], st), "event");
+    mark(6);
 }
 
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
@@ -353,18 +367,21 @@ void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, doubl
         else
             product_one<float>(op, trans, alpha, x + c * ldx, y + c * ldy, st);
     }
-    op.timed_valid = op.timing;
 }
 
 void phase_times(Op &op, double out[6])
 {
-    if (!op.timed_valid) fail(H2B_ESTATE, "no timed product recorded (enable timing first)");
-    hip_check(hipEventSynchronize(op.ev[6]), "event sync");
-    for (int i = 0; i < 6; ++i) {
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, op.ev[i], op.ev[i + 1]), "event time");
-        out[i] = ms;
-    }
+    if (op.nev == 0) fail(H2B_ESTATE, "no timed product recorded (enable timing first)");
+    hip_check(hipEventSynchronize(op.ev[op.nev - 1][6]), "event sync");
+    for (int i = 0; i < 6; ++i) out[i] = 0.0;
+    for (size_t k = 0; k < op.nev; ++k)
+        for (int i = 0; i < 6; ++i) {
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, op.ev[k][i], op.ev[k][i + 1]), "event time");
+            out[i] += ms;
+        }
+    for (int i = 0; i < 6; ++i) out[i] /= (double)op.nev;
+    op.nev = 0;
 }
 
 void op_stats(const Op &op, h2b_op_stats &s)
@@ -382,6 +399,8 @@ void op_stats(const Op &op, h2b_op_stats &s)
     s.bytes_near = op.near.total * 8;
     s.bytes_far = (s.coupling_entries + s.row_basis_entries + s.col_basis_entries) * fsz;
     s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.xhat.bytes + op.yhat.bytes);
+    s.row_coeffs = op.rowb->hat_total;
+    s.col_coeffs = op.colb->hat_total;
     auto rk = [](const Basis &B, int32_t &mx, double &mean) {
         mx = 0;
         double sum = 0;

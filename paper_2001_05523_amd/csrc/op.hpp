@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <memory>
 #include <utility>
 #include <vector>
@@ -47,8 +48,9 @@ struct Op {
     ColPanels cpl_T;
     DevMem cpl_vals;
     DevMem xp, yp, xhat, yhat;              // product work vectors
-    bool timing = false, timed_valid = false;
-    hipEvent_t ev[7] = {};
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 7>> ev;  // one event set per timed product
+    size_t nev = 0;                              // timed products since timing was enabled
     ~Op();
 };
 
