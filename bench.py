@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--q-near", type=int, default=6)
+    ap.add_argument("--tol", type=float, default=1e-6, help="recompression tolerance (0: off)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -109,7 +110,8 @@ def main():
     x_k = synth.random_vector(nv, 502)
 
     mesh = h2b.Mesh(verts, tris)
-    common = dict(leaf=args.leaf, order_m=args.order, q_near=args.q_near, mesh=mesh)
+    common = dict(leaf=args.leaf, order_m=args.order, q_near=args.q_near, mesh=mesh,
+                  recompress_tol=args.tol)
     ops, assembly_s = {}, {}
     kinds = [("G", "slp", "f64"), ("K", "dlp", "f64")]
     if not args.no_mixed:
@@ -120,9 +122,10 @@ def main():
         torch.cuda.synchronize()
         assembly_s[name] = time.perf_counter() - t0
         inf = ops[name].info()
-        log("assembled %s (%s): %.1f s, near %.2f GB, far %.2f GB, %d far / %d near blocks"
-            % (name, fd, assembly_s[name], inf["bytes_near"] / 1e9, inf["bytes_far"] / 1e9,
-               inf["nfar"], inf["nnear"]))
+        log("assembled %s (%s): %.1f s, near %.2f GB, far %.2f GB, %d far / %d near blocks, "
+            "mean rank %.1f / %.1f" % (name, fd, assembly_s[name], inf["bytes_near"] / 1e9,
+                                       inf["bytes_far"] / 1e9, inf["nfar"], inf["nnear"],
+                                       inf["mean_rank_row"], inf["mean_rank_col"]))
 
     Xg = torch.tensor(x_g, device=dev)
     Xk = torch.tensor(x_k, device=dev)
@@ -159,7 +162,9 @@ def main():
                  coupling_gbps=b["coupling"] / ph["coupling"] / 1e6,
                  near_gbps=b["near"] / ph["nearfield"] / 1e6,
                  bytes_near=inf["bytes_near"], bytes_far=inf["bytes_far"],
-                 nfar=inf["nfar"], nnear=inf["nnear"], assembly_s=assembly_s[name])
+                 nfar=inf["nfar"], nnear=inf["nnear"], assembly_s=assembly_s[name],
+                 mean_rank=(inf["mean_rank_row"], inf["mean_rank_col"]),
+                 max_rank=(inf["max_rank_row"], inf["max_rank_col"]))
         detail[name] = d
         if not name.endswith("32"):
             for kname, ms_k, by in (("coupling", ph["coupling"], b["coupling"]),
@@ -187,15 +192,15 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "unit sphere (octahedron split s=%d, %d triangles, %d vertices): one G x "
-                        "and one K x per step, H^2 Chebyshev order %d, leaf %d, eta 1, q_near %d"
-                        % (args.s, nt, nv, args.order, args.leaf, args.q_near),
+                        "and one K x per step, H^2 Chebyshev order %d recompressed to %g, leaf %d, "
+                        "eta 1, q_near %d" % (args.s, nt, nv, args.order, args.tol, args.leaf, args.q_near),
             "triangles": nt, "vertices": nv, "order_m": args.order, "leaf": args.leaf,
-            "q_near": args.q_near, "recompress_tol": 0.0, "x_seeds": [501, 502],
+            "q_near": args.q_near, "recompress_tol": args.tol, "x_seeds": [501, 502],
         },
         "step_gbps": round(step_bytes / ms64 / 1e6, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "%s %s panel product (k_rowpanel<double>)" % dominant[:2],
+            "kernel": "%s %s panel product (k_rowpanel<double, double, double, %d>)" % (dominant[0], dominant[1], 2 if dominant[1] == "coupling" else 3),
             "achieved": round(dominant[3] / dominant[2] / 1e6, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libh2bem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["host_trees.cpp", "kernels.hip", "op.hip", "capi.cpp"]
+SOURCES = ["host_trees.cpp", "host_linalg.cpp", "kernels.hip", "op.hip", "recompress.hip", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

@@ -53,15 +53,19 @@ void launch_coupling(const RowPanels &rp, const double *raxes, const double *cax
 
 // --------------------------------------------------------------- product
 
+// Step of the product a panel launch belongs to; each gets its own kernel
+// instance so that profiles tell them apart.
+enum class Role { Leaf, Transfer, Coupling, Near };
+
 // y[out_begin + r] (=|+=) sum_c vals[...] x[...] for groups [g0, g1).
 template <typename VT, typename XT, typename YT>
 void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     bool accumulate, hipStream_t st);
+                     bool accumulate, hipStream_t st, Role role);
 
 // y[out_begin + j] += sum over blocks of the transposed product, groups [g0, g1).
 template <typename VT, typename XT, typename YT>
 void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     hipStream_t st);
+                     hipStream_t st, Role role);
 
 // xp[k + c*n] = x[perm[k] + c*ldx]
 void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,

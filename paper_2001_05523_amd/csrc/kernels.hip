@@ -457,7 +457,7 @@ constexpr int CHUNK = 4096;  // input columns staged in LDS per pass
 // One workgroup per group: stage the input segments of a column chunk in LDS,
 // then every wave takes rows round-robin and streams its row of the panel with
 // coalesced loads; per-row partial sums live in LDS across chunks.
-template <typename VT, typename XT, typename YT>
+template <typename VT, typename XT, typename YT, int ROLE>
 __global__ __launch_bounds__(NT) void k_rowpanel(RowPanelDev d, int g0, const VT *__restrict__ vals,
                                                  const XT *__restrict__ x, YT *__restrict__ y,
                                                  int accumulate)
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_rowpanel(RowPanelDev d, int g0, const VT
 
 // One workgroup per output segment: lanes over output entries (64 at a time),
 // waves over the rows of all contributing blocks, partial sums reduced in LDS.
-template <typename VT, typename XT, typename YT>
+template <typename VT, typename XT, typename YT, int ROLE>
 __global__ __launch_bounds__(NT) void k_colpanel(ColPanelDev d, int g0, const VT *__restrict__ vals,
                                                  const XT *__restrict__ x, YT *__restrict__ y)
 {
@@ -640,22 +640,48 @@ void launch_coupling(const RowPanels &rp, const double *raxes, const double *cax
 
 template <typename VT, typename XT, typename YT>
 void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     bool accumulate, hipStream_t st)
+                     bool accumulate, hipStream_t st, Role role)
 {
     if (g1 <= g0) return;
     using A = typename Acc<VT>::type;
     const size_t shm = sizeof(A) * (CHUNK + (size_t)std::max(rp.max_nrows, 1));
-    hipLaunchKernelGGL((k_rowpanel<VT, XT, YT>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x,
-                       y, accumulate ? 1 : 0);
+    const int acc = accumulate ? 1 : 0;
+    switch (role) {
+    case Role::Leaf:
+        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 0>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
+        break;
+    case Role::Transfer:
+        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 1>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
+        break;
+    case Role::Coupling:
+        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 2>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
+        break;
+    default:
+        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 3>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
+        break;
+    }
     hip_check(hipGetLastError(), "row panel launch");
 }
 
 template <typename VT, typename XT, typename YT>
 void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     hipStream_t st)
+                     hipStream_t st, Role role)
 {
     if (g1 <= g0) return;
-    hipLaunchKernelGGL((k_colpanel<VT, XT, YT>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+    switch (role) {
+    case Role::Leaf:
+        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 0>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        break;
+    case Role::Transfer:
+        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 1>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        break;
+    case Role::Coupling:
+        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 2>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        break;
+    default:
+        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 3>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        break;
+    }
     hip_check(hipGetLastError(), "column panel launch");
 }
 
@@ -697,9 +723,9 @@ template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
 
 #define H2B_PANEL_INST(VT, XT, YT)                                                                      \
     template void launch_rowpanel<VT, XT, YT>(const RowPanels &, int, int, const VT *, const XT *, YT *, \
-                                              bool, hipStream_t);                                       \
+                                              bool, hipStream_t, Role);                                 \
     template void launch_colpanel<VT, XT, YT>(const ColPanels &, int, int, const VT *, const XT *, YT *, \
-                                              hipStream_t);
+                                              hipStream_t, Role);
 H2B_PANEL_INST(double, double, double)
 H2B_PANEL_INST(float, double, float)
 H2B_PANEL_INST(float, float, float)

@@ -21,6 +21,7 @@ void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp)
     std::vector<std::pair<int, int>> refs;
     for (int g = g0; g < g1; ++g)
         for (int s = rp.seg_ptr[g]; s < rp.seg_ptr[g + 1]; ++s) {
+            if (rp.seg_len[s] == 0 || rp.nrows[g] == 0) continue;  // contributes nothing
             by_out[rp.seg_in[s]].push_back((int)refs.size());
             out_len[rp.seg_in[s]] = rp.seg_len[s];
             refs.push_back({g, s});
@@ -68,12 +69,12 @@ static QuadDev make_quad(int q)
     return Q;
 }
 
-// Structure of a cluster basis with uniform rank k on every cluster.
-static void build_basis_structure(Basis &B, int k)
+// Structure of a cluster basis with the given rank per cluster.
+void build_basis_structure(Basis &B, const std::vector<int> &ranks)
 {
     const Tree &T = *B.tree;
     const int64_t nc = T.nclusters();
-    B.rank.assign(nc, k);
+    B.rank = ranks;
     B.hat_off.resize(nc + 1);
     B.hat_off[0] = 0;
     for (int64_t c = 0; c < nc; ++c) B.hat_off[c + 1] = B.hat_off[c] + B.rank[c];
@@ -158,7 +159,8 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (kernel == H2B_DLP && blocks->cols->space != H2B_P1)
         fail(H2B_EINVAL, "the double-layer matrix needs a P1 column tree");
     if (kernel != H2B_SLP && kernel != H2B_DLP) fail(H2B_EINVAL, "unknown kernel");
-    if (p.recompress_tol > 0.0) fail(H2B_ENOTSUP, "recompression is not available in this build");
+    if (p.recompress_tol > 0.0 && p.order_m > 4)
+        fail(H2B_ENOTSUP, "recompression supports order_m <= 4");
 
     auto op = std::make_unique<Op>();
     op->blocks = blocks;
@@ -206,7 +208,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     std::vector<Basis *> bases{op->rowb.get()};
     if (op->colb != op->rowb) bases.push_back(op->colb.get());
     for (Basis *B : bases) {
-        build_basis_structure(*B, k);
+        build_basis_structure(*B, std::vector<int>(B->tree->nclusters(), k));
         B->leaf.upload(st);
         B->leaf_T.upload(st);
         B->trans.upload(st);
@@ -253,29 +255,34 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     QuadDev Qn = make_quad(p.q_near);
     launch_near_assemble(kernel, op->near, op->rowb->perm_dev, op->colb->perm_dev, op->geo, Qn,
                          op->near_vals.as<double>(), st);
-    const size_t fsz = (p.farfield_dtype == H2B_F64) ? sizeof(double) : sizeof(float);
+    // with recompression the interpolation operator is built in FP64 first
+    const bool rc = p.recompress_tol > 0.0;
+    const h2b_dtype adt = rc ? H2B_F64 : p.farfield_dtype;
+    const size_t fsz = (adt == H2B_F64) ? sizeof(double) : sizeof(float);
     op->cpl_vals.alloc(fsz * std::max<int64_t>(op->cpl.total, 1));
     for (Basis *B : bases) {
-        if (p.farfield_dtype == H2B_F64)
+        if (adt == H2B_F64)
             assemble_basis<double>(*B, m, B->axes, op->geo, st);
         else
             assemble_basis<float>(*B, m, B->axes, op->geo, st);
     }
-    if (p.farfield_dtype == H2B_F64)
+    if (adt == H2B_F64)
         launch_coupling<double>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
                                 op->cpl_vals.as<double>(), st);
     else
         launch_coupling<float>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
                                op->cpl_vals.as<float>(), st);
     hip_check(hipStreamSynchronize(st), "assembly");
+    if (rc) recompress_op(*op, p.recompress_tol, st);
 
     // work vectors
+    const size_t wsz = (p.farfield_dtype == H2B_F64) ? sizeof(double) : sizeof(float);
     const int64_t nmax = std::max(op->nrows, op->ncols);
     const int64_t hmax = std::max(op->rowb->hat_total, op->colb->hat_total);
     op->xp.alloc(sizeof(double) * nmax);
     op->yp.alloc(sizeof(double) * nmax);
-    op->xhat.alloc(fsz * std::max<int64_t>(hmax, 1));
-    op->yhat.alloc(fsz * std::max<int64_t>(hmax, 1));
+    op->xhat.alloc(wsz * std::max<int64_t>(hmax, 1));
+    op->yhat.alloc(wsz * std::max<int64_t>(hmax, 1));
     return op;
 }
 
@@ -284,17 +291,21 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
 template <typename F>
 static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
 {
-    launch_rowpanel<F, double, F>(B.leaf, 0, B.leaf.ngroups(), B.leaf_vals.as<F>(), xp, xhat, false, st);
+    launch_rowpanel<F, double, F>(B.leaf, 0, B.leaf.ngroups(), B.leaf_vals.as<F>(), xp, xhat, false, st,
+                                  Role::Leaf);
     for (auto &s : B.fw_steps)
-        launch_rowpanel<F, F, F>(B.trans, s.first, s.second, B.trans_vals.as<F>(), xhat, xhat, false, st);
+        launch_rowpanel<F, F, F>(B.trans, s.first, s.second, B.trans_vals.as<F>(), xhat, xhat, false, st,
+                                 Role::Transfer);
 }
 
 template <typename F>
 static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 {
     for (auto &s : B.bw_steps)
-        launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), yhat, yhat, st);
-    launch_colpanel<F, F, double>(B.leaf_T, 0, B.leaf_T.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st);
+        launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), yhat, yhat, st,
+                                 Role::Transfer);
+    launch_colpanel<F, F, double>(B.leaf_T, 0, B.leaf_T.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st,
+                                  Role::Leaf);
 }
 
 // Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
@@ -329,18 +340,20 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     forward<F>(Bin, xp, xhat, st);
     mark(2);
     if (!trans)
-        launch_rowpanel<F, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, true, st);
+        launch_rowpanel<F, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, true, st,
+                                 Role::Coupling);
     else
-        launch_colpanel<F, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, st);
+        launch_colpanel<F, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, st,
+                                 Role::Coupling);
     mark(3);
     backward<F>(Bout, yhat, yp, st);
     mark(4);
     if (!trans)
         launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
-                                                xp, yp, true, st);
+                                                xp, yp, true, st, Role::Near);
     else
         launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
-                                                op.near_vals.as<double>(), xp, yp, st);
+                                                op.near_vals.as<double>(), xp, yp, st, Role::Near);
     mark(5);
     launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, y, nout, st);
     mark(6);

@@ -111,6 +111,49 @@ def test_h2_parity_against_oracle_h2(kernel, s, leaf, m):
         assert err_oracle < 1e-2
 
 
+@pytest.mark.parametrize("kernel,s,leaf", [("slp", 16, 16), ("dlp", 16, 16), ("slp", 16, 32)])
+def test_recompressed_against_oracle_h2(kernel, s, leaf):
+    """Algebraic recompression of the order-4 interpolation bases to 1e-6
+    (relative per cluster): the product stays within a small multiple of the
+    tolerance of the oracle's (uncompressed) H^2 matrix while the ranks drop."""
+    h = _lib()
+    v, t = synth.octa_sphere(s)
+    q, m, tol = 4, 4, 1e-6
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=m, q_near=q, recompress_tol=tol)
+    info = op.info()
+    assert info["mean_rank_row"] < m ** 3 and info["max_rank_row"] <= m ** 3
+    A = _dense(s, kernel, q)
+    H, _ = h2.h2_dense(v, t, kernel, leaf, m, near_matrix=A)
+    for trans in (False, True):
+        nin = A.shape[0] if trans else A.shape[1]
+        x = synth.random_vector(nin, 5 + trans)
+        y = _run(op, x, trans=trans)
+        Hx = (H.T if trans else H) @ x
+        err = np.linalg.norm(y - Hx) / np.linalg.norm(Hx)
+        print("%s trans=%d recompressed vs oracle H2: %.3e, mean rank %.1f / %.1f"
+              % (kernel, trans, err, info["mean_rank_row"], info["mean_rank_col"]))
+        assert err <= 20 * tol
+
+
+def test_recompressed_mixed_precision():
+    """FP32 storage of the recompressed (orthonormal) bases and couplings stays
+    within 1e-5 of the FP64 recompressed product."""
+    h = _lib()
+    v, t = synth.octa_sphere(32)
+    for kernel in ("slp", "dlp"):
+        op64 = h.Operator(v, t, kernel=kernel, leaf=32, order_m=4, q_near=4, recompress_tol=1e-6)
+        op32 = h.Operator(v, t, kernel=kernel, leaf=32, order_m=4, q_near=4, recompress_tol=1e-6,
+                          farfield_dtype="f32")
+        for trans in (False, True):
+            nin = op64.shape[0] if trans else op64.shape[1]
+            x = synth.random_vector(nin, 13)
+            y64 = _run(op64, x, trans=trans)
+            y32 = _run(op32, x, trans=trans)
+            d = np.linalg.norm(y32 - y64) / np.linalg.norm(y64)
+            print("%s trans=%d mixed vs fp64 (recompressed): %.3e" % (kernel, trans, d))
+            assert d <= 1e-5
+
+
 def test_mixed_precision_far_field():
     """FP32 bases and coupling matrices with FP32 accumulation; near field FP64.
     Relative difference to the FP64 product <= 1e-5."""
