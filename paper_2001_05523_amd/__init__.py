@@ -6,7 +6,7 @@ for x and y) and streams.  The functions keep the C names of include/h2bem.h;
 ``Mesh``, ``Tree``, ``Blocks`` and ``Operator`` are small owners of the handles.
 
 Importing this package loads the library and fails loudly if it has not been
-built (``python -m paper_2001_05523_amd.build``).
+built (``python paper_2001_05523_amd/csrc/build_lib.py``).
 """
 import ctypes
 import os
@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libh2bem.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libh2bem.so is not built: run `python -m paper_2001_05523_amd.build` "
+    raise ImportError("libh2bem.so is not built: run `python paper_2001_05523_amd/csrc/build_lib.py` "
                       "(expected at %s)" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -113,9 +113,9 @@ class Mesh:
         self.handle = h
         self.nv, self.nt = len(v), len(t)
 
-    def __del__(self):
+    def __del__(self, _destroy=h2b_mesh_destroy):
         if getattr(self, "handle", None):
-            h2b_mesh_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -137,9 +137,9 @@ class Tree:
         _check(h2b_tree_arrays(self.handle, _ptr(perm), _ptr(b), _ptr(e), _ptr(par), _ptr(box)))
         return dict(perm=perm, begin=b, end=e, parent=par, box=box)
 
-    def __del__(self):
+    def __del__(self, _destroy=h2b_tree_destroy):
         if getattr(self, "handle", None):
-            h2b_tree_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -159,9 +159,9 @@ class Blocks:
         _check(h2b_blocks_lists(self.handle, _ptr(far), _ptr(near)))
         return far, near
 
-    def __del__(self):
+    def __del__(self, _destroy=h2b_blocks_destroy):
         if getattr(self, "handle", None):
-            h2b_blocks_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -234,7 +234,7 @@ class Operator:
         _check(h2b_op_phase_times(self.handle, _ptr(out)))
         return dict(zip(("gather", "forward", "coupling", "backward", "nearfield", "scatter"), out))
 
-    def __del__(self):
+    def __del__(self, _destroy=h2b_op_destroy):
         if getattr(self, "handle", None):
-            h2b_op_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None

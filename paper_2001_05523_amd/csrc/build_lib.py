@@ -1,16 +1,19 @@
 """Build the HIP library libh2bem.so for gfx950 (in-tree, no JIT cache).
 
-    python -m paper_2001_05523_amd.build
+    python paper_2001_05523_amd/csrc/build_lib.py
+
+Runs as a plain script (it does not import the package, whose import loads
+the library).
 """
 import concurrent.futures
 import os
 import subprocess
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
-CSRC = os.path.join(HERE, "csrc")
-OUT_DIR = os.path.join(HERE, "lib")
+CSRC = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.dirname(CSRC)
+ROOT = os.path.dirname(PKG)
+OUT_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(OUT_DIR, "libh2bem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["host_trees.cpp", "host_linalg.cpp", "kernels.hip", "op.hip", "recompress.hip", "capi.cpp"]

@@ -452,38 +452,40 @@ template <typename A> __device__ inline A wave_sum(A v)
     return v;
 }
 
-constexpr int CHUNK = 4096;  // input columns staged in LDS per pass
+constexpr int CHUNK = 4096;  // largest number of input columns staged in LDS per pass
 
-// One workgroup per group: stage the input segments of a column chunk in LDS,
-// then every wave takes rows round-robin and streams its row of the panel with
-// coalesced loads; per-row partial sums live in LDS across chunks.
-template <typename VT, typename XT, typename YT, int ROLE>
-__global__ __launch_bounds__(NT) void k_rowpanel(RowPanelDev d, int g0, const VT *__restrict__ vals,
-                                                 const XT *__restrict__ x, YT *__restrict__ y,
-                                                 int accumulate)
+template <typename T> __device__ inline T stream_load(const T *p) { return __builtin_nontemporal_load(p); }
+
+// One workgroup of NW waves per group: stage the input segments of a column
+// chunk in LDS, then every wave takes two rows at a time and streams them with
+// coalesced non-temporal loads (8 in flight per lane); per-row partial sums
+// live in LDS across chunks.
+template <typename VT, typename XT, typename YT, int ROLE, int NW>
+__global__ __launch_bounds__(NW * 64) void k_rowpanel(RowPanelDev d, int g0, int chunk,
+                                                      const VT *__restrict__ vals,
+                                                      const XT *__restrict__ x, YT *__restrict__ y,
+                                                      int accumulate)
 {
     using A = typename Acc<VT>::type;
+    constexpr int NTH = NW * 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *xs = reinterpret_cast<A *>(smem_raw);
-    A *racc = xs + CHUNK;
+    A *racc = xs + chunk;
     const int g = g0 + blockIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
     const int64_t off = d.val_off[g];
-    const int sp0 = d.seg_ptr[g];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int NW = NT / 64;
 
-    int seg = sp0, seg_pos = 0;  // staging cursor over the segments
-    for (int c0 = 0; c0 < nc; c0 += CHUNK) {
-        const int clen = min(CHUNK, nc - c0);
-        // stage columns [c0, c0 + clen)
+    int seg = d.seg_ptr[g], seg_pos = 0;  // staging cursor over the segments
+    for (int c0 = 0; c0 < nc; c0 += chunk) {
+        const int clen = min(chunk, nc - c0);
         {
             int filled = 0;
             int s = seg, p = seg_pos;
             while (filled < clen) {
                 const int len = min(d.seg_len[s] - p, clen - filled);
                 const XT *src = x + d.seg_in[s] + p;
-                for (int j = threadIdx.x; j < len; j += NT) xs[filled + j] = (A)src[j];
+                for (int j = threadIdx.x; j < len; j += NTH) xs[filled + j] = (A)src[j];
                 filled += len;
                 p += len;
                 if (p == d.seg_len[s]) {
@@ -495,24 +497,43 @@ __global__ __launch_bounds__(NT) void k_rowpanel(RowPanelDev d, int g0, const VT
             seg_pos = p;
         }
         __syncthreads();
-        for (int r = wave; r < nr; r += NW) {
-            const VT *row = vals + off + (int64_t)r * nc + c0;
-            A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int r = 2 * wave; r < nr; r += 2 * NW) {
+            const VT *row0 = vals + off + (int64_t)r * nc + c0;
+            // an odd last row is paired with itself (the repeat hits in cache)
+            const VT *row1 = (r + 1 < nr) ? row0 + nc : row0;
+            A a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
             int c = lane;
             for (; c + 192 < clen; c += 256) {
-                s0 += (A)row[c] * xs[c];
-                s1 += (A)row[c + 64] * xs[c + 64];
-                s2 += (A)row[c + 128] * xs[c + 128];
-                s3 += (A)row[c + 192] * xs[c + 192];
+                const VT p0 = stream_load(row0 + c), p1 = stream_load(row0 + c + 64);
+                const VT p2 = stream_load(row0 + c + 128), p3 = stream_load(row0 + c + 192);
+                const VT q0 = stream_load(row1 + c), q1 = stream_load(row1 + c + 64);
+                const VT q2 = stream_load(row1 + c + 128), q3 = stream_load(row1 + c + 192);
+                const A x0 = xs[c], x1 = xs[c + 64], x2 = xs[c + 128], x3 = xs[c + 192];
+                a0 += (A)p0 * x0;
+                a1 += (A)p1 * x1;
+                a2 += (A)p2 * x2;
+                a3 += (A)p3 * x3;
+                b0 += (A)q0 * x0;
+                b1 += (A)q1 * x1;
+                b2 += (A)q2 * x2;
+                b3 += (A)q3 * x3;
             }
-            for (; c < clen; c += 64) s0 += (A)row[c] * xs[c];
-            A s = wave_sum((s0 + s1) + (s2 + s3));
-            if (lane == 0) racc[r] = (c0 == 0) ? s : racc[r] + s;
+            for (; c < clen; c += 64) {
+                const A xv = xs[c];
+                a0 += (A)stream_load(row0 + c) * xv;
+                b0 += (A)stream_load(row1 + c) * xv;
+            }
+            const A sa = wave_sum((a0 + a1) + (a2 + a3));
+            const A sb = wave_sum((b0 + b1) + (b2 + b3));
+            if (lane == 0) {
+                racc[r] = (c0 == 0) ? sa : racc[r] + sa;
+                if (r + 1 < nr) racc[r + 1] = (c0 == 0) ? sb : racc[r + 1] + sb;
+            }
         }
         __syncthreads();
     }
     const int ob = d.out_begin[g];
-    for (int r = threadIdx.x; r < nr; r += NT) {
+    for (int r = threadIdx.x; r < nr; r += NTH) {
         const A v = (nc > 0) ? racc[r] : A(0);
         if (accumulate)
             y[ob + r] = (YT)((A)y[ob + r] + v);
@@ -546,8 +567,21 @@ __global__ __launch_bounds__(NT) void k_colpanel(ColPanelDev d, int g0, const VT
             const XT *xin = x + d.b_in[b];
             int i = (wave - base) % NW;
             if (i < 0) i += NW;
-            if (valid)
-                for (; i < nrb; i += NW) acc += (A)col[i * stride] * (A)xin[i];
+            if (valid) {
+                A a1 = 0, a2 = 0, a3 = 0;
+                for (; i + 3 * NW < nrb; i += 4 * NW) {
+                    const VT v0 = stream_load(col + i * stride);
+                    const VT v1 = stream_load(col + (i + NW) * stride);
+                    const VT v2 = stream_load(col + (i + 2 * NW) * stride);
+                    const VT v3 = stream_load(col + (i + 3 * NW) * stride);
+                    acc += (A)v0 * (A)xin[i];
+                    a1 += (A)v1 * (A)xin[i + NW];
+                    a2 += (A)v2 * (A)xin[i + 2 * NW];
+                    a3 += (A)v3 * (A)xin[i + 3 * NW];
+                }
+                for (; i < nrb; i += NW) acc += (A)stream_load(col + i * stride) * (A)xin[i];
+                acc += (a1 + a2) + a3;
+            }
             base += nrb;
         }
         red[wave][lane] = acc;
@@ -638,27 +672,44 @@ void launch_coupling(const RowPanels &rp, const double *raxes, const double *cax
     hip_check(hipGetLastError(), "coupling launch");
 }
 
+template <typename VT, typename XT, typename YT, int ROLE, int NW>
+static void rowpanel_nw(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, int acc,
+                        hipStream_t st)
+{
+    using A = typename Acc<VT>::type;
+    int chunk = std::min(CHUNK, std::max(64, (rp.max_ncols + 63) / 64 * 64));
+    if (NW == 1) chunk = std::min(chunk, 1024);
+    const size_t shm = sizeof(A) * ((size_t)chunk + (size_t)std::max(rp.max_nrows, 1));
+    hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, ROLE, NW>), dim3(g1 - g0), dim3(NW * 64), shm, st, rp.dev, g0,
+                       chunk, vals, x, y, acc);
+}
+
+template <typename VT, typename XT, typename YT, int ROLE>
+static void rowpanel_role(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, int acc,
+                          hipStream_t st)
+{
+    // small panels (recompressed coupling, leaf and transfer matrices) get one
+    // wave per group so that many groups stream concurrently; tall panels
+    // (near field) share the staged input among four waves
+    const double rows_per_group = (double)rp.total / std::max<int64_t>(1, (int64_t)rp.ngroups()) /
+                                  std::max(1.0, (double)rp.max_ncols);
+    if (rp.max_nrows <= 32 || rows_per_group < 16)
+        rowpanel_nw<VT, XT, YT, ROLE, 1>(rp, g0, g1, vals, x, y, acc, st);
+    else
+        rowpanel_nw<VT, XT, YT, ROLE, 4>(rp, g0, g1, vals, x, y, acc, st);
+}
+
 template <typename VT, typename XT, typename YT>
 void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
                      bool accumulate, hipStream_t st, Role role)
 {
     if (g1 <= g0) return;
-    using A = typename Acc<VT>::type;
-    const size_t shm = sizeof(A) * (CHUNK + (size_t)std::max(rp.max_nrows, 1));
     const int acc = accumulate ? 1 : 0;
     switch (role) {
-    case Role::Leaf:
-        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 0>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
-        break;
-    case Role::Transfer:
-        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 1>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
-        break;
-    case Role::Coupling:
-        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 2>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
-        break;
-    default:
-        hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, 3>), dim3(g1 - g0), dim3(NT), shm, st, rp.dev, g0, vals, x, y, acc);
-        break;
+    case Role::Leaf: rowpanel_role<VT, XT, YT, 0>(rp, g0, g1, vals, x, y, acc, st); break;
+    case Role::Transfer: rowpanel_role<VT, XT, YT, 1>(rp, g0, g1, vals, x, y, acc, st); break;
+    case Role::Coupling: rowpanel_role<VT, XT, YT, 2>(rp, g0, g1, vals, x, y, acc, st); break;
+    default: rowpanel_role<VT, XT, YT, 3>(rp, g0, g1, vals, x, y, acc, st); break;
     }
     hip_check(hipGetLastError(), "row panel launch");
 }
@@ -720,7 +771,6 @@ template void launch_coupling<float>(const RowPanels &, const double *, const do
                                      hipStream_t);
 template void launch_fill_zero<double>(double *, int64_t, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
-
 #define H2B_PANEL_INST(VT, XT, YT)                                                                      \
     template void launch_rowpanel<VT, XT, YT>(const RowPanels &, int, int, const VT *, const XT *, YT *, \
                                               bool, hipStream_t, Role);                                 \

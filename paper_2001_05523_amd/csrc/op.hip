@@ -70,7 +70,7 @@ static QuadDev make_quad(int q)
 }
 
 // Structure of a cluster basis with the given rank per cluster.
-void build_basis_structure(Basis &B, const std::vector<int> &ranks)
+void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st)
 {
     const Tree &T = *B.tree;
     const int64_t nc = T.nclusters();
@@ -208,7 +208,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     std::vector<Basis *> bases{op->rowb.get()};
     if (op->colb != op->rowb) bases.push_back(op->colb.get());
     for (Basis *B : bases) {
-        build_basis_structure(*B, std::vector<int>(B->tree->nclusters(), k));
+        build_basis_structure(*B, std::vector<int>(B->tree->nclusters(), k), st);
         B->leaf.upload(st);
         B->leaf_T.upload(st);
         B->trans.upload(st);

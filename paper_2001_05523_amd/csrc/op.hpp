@@ -56,7 +56,7 @@ struct Op {
 
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
-void build_basis_structure(Basis &B, const std::vector<int> &ranks);
+void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);

@@ -574,7 +574,7 @@ void recompress_op(Op &op, double tol, hipStream_t st)
         B.leaf_T = ColPanels();
         B.trans = RowPanels();
         B.trans_T = ColPanels();
-        build_basis_structure(B, orth[bi].kk);
+        build_basis_structure(B, orth[bi].kk, st);
         B.leaf.upload(st);
         B.leaf_T.upload(st);
         B.trans.upload(st);
