@@ -62,10 +62,14 @@ template <typename VT, typename XT, typename YT>
 void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y,
                      bool accumulate, hipStream_t st, Role role);
 
-// y[out_begin + j] += sum over blocks of the transposed product, groups [g0, g1).
+// y[out_begin + j] (+)= sum over blocks of the transposed product, groups [g0, g1)
+// (overwrite only for the leaf and transfer roles).
 template <typename VT, typename XT, typename YT>
 void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     hipStream_t st, Role role);
+                     hipStream_t st, Role role, bool accumulate = true);
+
+// out = per-group transpose of the panels of rp (same offsets).
+template <typename T> void launch_transpose_panels(const RowPanels &rp, const T *in, T *out, hipStream_t st);
 
 // xp[k + c*n] = x[perm[k] + c*ldx]
 void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,

@@ -672,6 +672,56 @@ void launch_coupling(const RowPanels &rp, const double *raxes, const double *cax
     hip_check(hipGetLastError(), "coupling launch");
 }
 
+// Narrow panels (leaf and transfer matrices, at most 128 input columns): one
+// wave per group, input in LDS, eight rows per iteration so that eight
+// independent loads per lane are in flight before the reductions.
+template <typename VT, typename XT, typename YT, int ROLE>
+__global__ __launch_bounds__(64) void k_rowpanel_narrow(RowPanelDev d, int g0, const VT *__restrict__ vals,
+                                                        const XT *__restrict__ x, YT *__restrict__ y,
+                                                        int accumulate)
+{
+    using A = typename Acc<VT>::type;
+    __shared__ A xs[128];
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int lane = threadIdx.x;
+    {
+        int filled = 0;
+        for (int s = d.seg_ptr[g]; s < d.seg_ptr[g + 1]; ++s) {
+            const int len = d.seg_len[s];
+            const XT *src = x + d.seg_in[s];
+            for (int j = lane; j < len; j += 64) xs[filled + j] = (A)src[j];
+            filled += len;
+        }
+    }
+    __syncthreads();
+    const A x0 = (lane < nc) ? xs[lane] : A(0);
+    const A x1 = (lane + 64 < nc) ? xs[lane + 64] : A(0);
+    const int ob = d.out_begin[g];
+    for (int r = 0; r < nr; r += 8) {
+        A acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc[q] = 0;
+            const int rr = min(r + q, nr - 1);
+            const VT *row = vals + off + (int64_t)rr * nc;
+            if (lane < nc) acc[q] += (A)row[lane] * x0;
+            if (lane + 64 < nc) acc[q] += (A)row[lane + 64] * x1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const A v = wave_sum(acc[q]);
+            if (lane == 0 && r + q < nr) {
+                if (accumulate)
+                    y[ob + r + q] = (YT)((A)y[ob + r + q] + v);
+                else
+                    y[ob + r + q] = (YT)v;
+            }
+        }
+    }
+}
+
 template <typename VT, typename XT, typename YT, int ROLE, int NW>
 static void rowpanel_nw(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, int acc,
                         hipStream_t st)
@@ -693,6 +743,11 @@ static void rowpanel_role(const RowPanels &rp, int g0, int g1, const VT *vals, c
     // (near field) share the staged input among four waves
     const double rows_per_group = (double)rp.total / std::max<int64_t>(1, (int64_t)rp.ngroups()) /
                                   std::max(1.0, (double)rp.max_ncols);
+    if (rp.max_ncols <= 128 && (ROLE == 0 || ROLE == 1)) {
+        hipLaunchKernelGGL((k_rowpanel_narrow<VT, XT, YT, ROLE>), dim3(g1 - g0), dim3(64), 0, st, rp.dev, g0, vals,
+                           x, y, acc);
+        return;
+    }
     if (rp.max_nrows <= 32 || rows_per_group < 16)
         rowpanel_nw<VT, XT, YT, ROLE, 1>(rp, g0, g1, vals, x, y, acc, st);
     else
@@ -714,17 +769,70 @@ void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const 
     hip_check(hipGetLastError(), "row panel launch");
 }
 
+// sum_i col[i * stride] * v[i] with eight independent loads in flight.
+template <typename VT, typename XT, typename A>
+__device__ inline A column_dot(const VT *__restrict__ col, int64_t stride, const XT *__restrict__ v, int n)
+{
+    A a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = 0;
+    for (; i + 7 < n; i += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += (A)col[(i + q) * stride] * (A)v[i + q];
+    }
+    for (; i < n; ++i) a[0] += (A)col[i * stride] * (A)v[i];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Transposed product of narrow panels (leaf and transfer matrices): one wave per
+// output segment, lanes over its entries, rows of each block with eight loads
+// in flight; no cross-wave reduction.
+template <typename VT, typename XT, typename YT, int ROLE>
+__global__ __launch_bounds__(64) void k_colpanel_narrow(ColPanelDev d, int g0, const VT *__restrict__ vals,
+                                                        const XT *__restrict__ x, YT *__restrict__ y,
+                                                        int accumulate)
+{
+    using A = typename Acc<VT>::type;
+    const int g = g0 + blockIdx.x;
+    const int ob = d.out_begin[g], ol = d.out_len[g];
+    const int b0 = d.blk_ptr[g], b1 = d.blk_ptr[g + 1];
+    for (int j = threadIdx.x; j < ol; j += 64) {
+        A acc = 0;
+        for (int b = b0; b < b1; ++b)
+            acc += column_dot<VT, XT, A>(vals + d.b_val_off[b] + d.b_c0[b] + j, d.b_stride[b], x + d.b_in[b],
+                                         d.b_nrows[b]);
+        y[ob + j] = accumulate ? (YT)((A)y[ob + j] + acc) : (YT)acc;
+    }
+}
+
+// Transposes every group's panel in place of a second buffer: out holds P^T
+// (ncols x nrows, row-major) at the group's offset.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_panels(RowPanelDev d, const T *__restrict__ in,
+                                                          T *__restrict__ out)
+{
+    const int g = blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    for (int e = threadIdx.x; e < nr * nc; e += 256) {
+        const int r = e / nc, c = e % nc;
+        out[off + (int64_t)c * nr + r] = in[off + e];
+    }
+}
+
 template <typename VT, typename XT, typename YT>
 void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
-                     hipStream_t st, Role role)
+                     hipStream_t st, Role role, bool accumulate)
 {
     if (g1 <= g0) return;
+    const int acc = accumulate ? 1 : 0;
     switch (role) {
     case Role::Leaf:
-        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 0>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        hipLaunchKernelGGL((k_colpanel_narrow<VT, XT, YT, 0>), dim3(g1 - g0), dim3(64), 0, st, cp.dev, g0, vals, x,
+                           y, acc);
         break;
     case Role::Transfer:
-        hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 1>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
+        hipLaunchKernelGGL((k_colpanel_narrow<VT, XT, YT, 1>), dim3(g1 - g0), dim3(64), 0, st, cp.dev, g0, vals, x,
+                           y, acc);
         break;
     case Role::Coupling:
         hipLaunchKernelGGL((k_colpanel<VT, XT, YT, 2>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, x, y);
@@ -734,6 +842,13 @@ void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const 
         break;
     }
     hip_check(hipGetLastError(), "column panel launch");
+}
+
+template <typename T> void launch_transpose_panels(const RowPanels &rp, const T *in, T *out, hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_transpose_panels<T>, dim3(rp.ngroups()), dim3(256), 0, st, rp.dev, in, out);
+    hip_check(hipGetLastError(), "transpose launch");
 }
 
 void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,
@@ -771,11 +886,13 @@ template void launch_coupling<float>(const RowPanels &, const double *, const do
                                      hipStream_t);
 template void launch_fill_zero<double>(double *, int64_t, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
+template void launch_transpose_panels<double>(const RowPanels &, const double *, double *, hipStream_t);
+template void launch_transpose_panels<float>(const RowPanels &, const float *, float *, hipStream_t);
 #define H2B_PANEL_INST(VT, XT, YT)                                                                      \
     template void launch_rowpanel<VT, XT, YT>(const RowPanels &, int, int, const VT *, const XT *, YT *, \
                                               bool, hipStream_t, Role);                                 \
     template void launch_colpanel<VT, XT, YT>(const ColPanels &, int, int, const VT *, const XT *, YT *, \
-                                              hipStream_t, Role);
+                                              hipStream_t, Role, bool);
 H2B_PANEL_INST(double, double, double)
 H2B_PANEL_INST(float, double, float)
 H2B_PANEL_INST(float, float, float)

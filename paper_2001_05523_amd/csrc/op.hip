@@ -69,6 +69,28 @@ static QuadDev make_quad(int q)
     return Q;
 }
 
+// Column panels of the forward products over transposed panel copies: one
+// output group per row-panel group, one block per segment (P^T rows of that
+// segment, row stride = the group's row count).
+static void forward_panels(const RowPanels &rp, ColPanels &cp)
+{
+    for (int g = 0; g < rp.ngroups(); ++g) {
+        cp.out_begin.push_back(rp.out_begin[g]);
+        cp.out_len.push_back(rp.nrows[g]);
+        cp.max_out = std::max(cp.max_out, rp.nrows[g]);
+        int c0 = 0;
+        for (int s = rp.seg_ptr[g]; s < rp.seg_ptr[g + 1]; ++s) {
+            cp.b_val_off.push_back(rp.val_off[g] + (int64_t)c0 * rp.nrows[g]);
+            cp.b_stride.push_back(rp.nrows[g]);
+            cp.b_c0.push_back(0);
+            cp.b_nrows.push_back(rp.seg_len[s]);
+            cp.b_in.push_back(rp.seg_in[s]);
+            c0 += rp.seg_len[s];
+        }
+        cp.blk_ptr.push_back((int32_t)cp.b_in.size());
+    }
+}
+
 // Structure of a cluster basis with the given rank per cluster.
 void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st)
 {
@@ -107,7 +129,27 @@ void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t 
         transpose_panels(B.trans, it->first, it->second, B.trans_T);
         B.bw_steps.push_back({o0, B.trans_T.ngroups()});
     }
+    forward_panels(B.leaf, B.leaf_F);
+    forward_panels(B.trans, B.trans_F);
+    B.leaf_F.upload(st);
+    B.trans_F.upload(st);
 }
+
+void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st)
+{
+    const size_t esz = (dt == H2B_F64) ? sizeof(double) : sizeof(float);
+    B.leafT_vals.alloc(esz * std::max<int64_t>(B.leaf.total, 1));
+    B.transT_vals.alloc(esz * std::max<int64_t>(B.trans.total, 1));
+    if (dt == H2B_F64) {
+        launch_transpose_panels<double>(B.leaf, B.leaf_vals.as<double>(), B.leafT_vals.as<double>(), st);
+        launch_transpose_panels<double>(B.trans, B.trans_vals.as<double>(), B.transT_vals.as<double>(), st);
+    } else {
+        launch_transpose_panels<float>(B.leaf, B.leaf_vals.as<float>(), B.leafT_vals.as<float>(), st);
+        launch_transpose_panels<float>(B.trans, B.trans_vals.as<float>(), B.transT_vals.as<float>(), st);
+    }
+    hip_check(hipStreamSynchronize(st), "basis transpose");
+}
+
 
 template <typename T>
 static void assemble_basis(Basis &B, int m, const DevMem &axes, const GeoDev &geo, hipStream_t st)
@@ -265,6 +307,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
             assemble_basis<double>(*B, m, B->axes, op->geo, st);
         else
             assemble_basis<float>(*B, m, B->axes, op->geo, st);
+        transpose_basis_values(*B, adt, st);
     }
     if (adt == H2B_F64)
         launch_coupling<double>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
@@ -291,11 +334,11 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
 template <typename F>
 static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
 {
-    launch_rowpanel<F, double, F>(B.leaf, 0, B.leaf.ngroups(), B.leaf_vals.as<F>(), xp, xhat, false, st,
-                                  Role::Leaf);
+    launch_colpanel<F, double, F>(B.leaf_F, 0, B.leaf_F.ngroups(), B.leafT_vals.as<F>(), xp, xhat, st,
+                                  Role::Leaf, false);
     for (auto &s : B.fw_steps)
-        launch_rowpanel<F, F, F>(B.trans, s.first, s.second, B.trans_vals.as<F>(), xhat, xhat, false, st,
-                                 Role::Transfer);
+        launch_colpanel<F, F, F>(B.trans_F, s.first, s.second, B.transT_vals.as<F>(), xhat, xhat, st,
+                                 Role::Transfer, false);
 }
 
 template <typename F>

@@ -28,6 +28,9 @@ struct Basis {
     std::vector<std::pair<int, int>> fw_steps;  // group ranges of trans, bottom-up
     std::vector<std::pair<int, int>> bw_steps;  // group ranges of trans_T, top-down
     DevMem leaf_vals, trans_vals;
+    // forward transformation as column products over transposed copies
+    ColPanels leaf_F, trans_F;              // one output group per row-panel group
+    DevMem leafT_vals, transT_vals;
     DevMem axes;                            // Chebyshev points, 3*m per cluster
     DevMem perm_mem;
     const int32_t *perm_dev = nullptr;
@@ -57,6 +60,8 @@ struct Op {
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
 void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st);
+// Transposed copies of the leaf and transfer values (after they are final).
+void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);

@@ -574,12 +574,15 @@ void recompress_op(Op &op, double tol, hipStream_t st)
         B.leaf_T = ColPanels();
         B.trans = RowPanels();
         B.trans_T = ColPanels();
+        B.leaf_F = ColPanels();
+        B.trans_F = ColPanels();
         build_basis_structure(B, orth[bi].kk, st);
         B.leaf.upload(st);
         B.leaf_T.upload(st);
         B.trans.upload(st);
         B.trans_T.upload(st);
         set_basis_values(B, orth[bi], op.params.farfield_dtype, st);
+        transpose_basis_values(B, op.params.farfield_dtype, st);
     }
 
     // 5. S'' = B_t S~ B_s^T
