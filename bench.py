@@ -26,6 +26,32 @@ import numpy as np
 
 METRIC = "H² G/K matvec ms & HBM GB/s at 2M triangles; mixed vs FP64 at rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["kernels.hip", "op.hip", "recompress.hip", "panels.hpp", "device.hpp", "op.hpp"]
+
+
+def sources_digest():
+    """sha256 over the library sources that define the product kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2001_05523_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic.json), or None when the kernels or the workload changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256") != sources_digest() or rec.get("config") != config:
+        return None
+    return rec.get("traffic_bytes", {}).get(kernel)
 
 
 def log(msg):
@@ -176,6 +202,8 @@ def main():
             a, r = y[base + "32"], y[base]
             detail[base + "32"]["rel_diff_vs_fp64"] = float(np.linalg.norm(a - r) / np.linalg.norm(r))
     step_bytes = detail["G"]["alg_bytes"] + detail["K"]["alg_bytes"]
+    traffic_config = {"s": args.s, "leaf": args.leaf, "order": args.order, "q_near": args.q_near,
+                      "tol": args.tol}
 
     out = {
         "metric": METRIC,
@@ -200,12 +228,15 @@ def main():
         "step_gbps": round(step_bytes / ms64 / 1e6, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "%s %s panel product (k_rowpanel<double, double, double, %d>)" % (dominant[0], dominant[1], 2 if dominant[1] == "coupling" else 3),
+            "kernel": "%s %s panel product (k_rowpanel<double, double, double, %d, *>)"
+                      % (dominant[0], dominant[1], 2 if dominant[1] == "coupling" else 3),
             "achieved": round(dominant[3] / dominant[2] / 1e6, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(dominant[3] / dominant[2] / 1e6 / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic("%s %s" % dominant[:2], traffic_config),
+            "alg_bytes": dominant[3],
+            "avg_launch_ms": round(dominant[2], 4),
         },
         "detail": detail,
     }

@@ -53,12 +53,16 @@ typedef enum {
 
 typedef enum { H2B_P0 = 0, H2B_P1 = 1 } h2b_space;        /* triangles (I) / vertices (J) */
 typedef enum { H2B_SLP = 0, H2B_DLP = 1 } h2b_kernel;     /* G (P0 x P0) / K (P0 x P1) */
-typedef enum { H2B_F64 = 0, H2B_F32 = 1 } h2b_dtype;
+/* Far-field storage: F64 everything double; F32 bases, coupling matrices and
+ * cluster coefficients float with float accumulation; BF16 as F32 but the
+ * coupling matrices stored in bfloat16.  The near field is always double. */
+typedef enum { H2B_F64 = 0, H2B_F32 = 1, H2B_BF16 = 2 } h2b_dtype;
 
 typedef struct h2b_mesh_s *h2b_mesh;
 typedef struct h2b_tree_s *h2b_tree;
 typedef struct h2b_blocks_s *h2b_blocks;
 typedef struct h2b_op_s *h2b_op;
+typedef struct h2b_batch_s *h2b_batch;
 
 /* Thread-local text of the last error ("" if none). */
 const char *h2b_last_error(void);
@@ -182,10 +186,43 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
  * transformation down the row tree, and the nearfield blocks.
  * x: device array of (trans ? rows : cols) x nrhs doubles, column j at x + j*ldx;
  * y: device array of (trans ? cols : rows) x nrhs doubles, column j at y + j*ldy.
+ * With nrhs > 1 the right-hand sides are processed in blocks (16, 32 or 64
+ * columns, chosen by h2b_op_tune or from nrhs) as small GEMMs that read every
+ * stored matrix once per block; the coupling product of the F32/BF16 far field
+ * runs on matrix cores (MFMA) with FP32 accumulation.  The first call with
+ * nrhs > 1 allocates the block work vectors unless h2b_op_tune did.
  * Runs asynchronously on hip_stream.  x and y must not overlap.
  * Errors: H2B_EINVAL (NULL pointers, nrhs < 1 or > 64, ld too small), H2B_EDEVICE. */
 h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
+
+/* Batched products over several operators (e.g. meshes of different sizes):
+ * captures y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  Each
+ * operator runs on its own stream forked from hip_stream inside the capture,
+ * so the products of different operators are concurrent branches of the graph.
+ * The arrays give per-operator arguments as for h2b_matvec; the device
+ * vectors are bound at creation and must stay valid while the batch exists.
+ * Creation checks every argument first and allocates each operator's work
+ * vectors; h2b_batch_launch then replays the graph on hip_stream.
+ * The batch keeps no reference to the operators: they must outlive it, and an
+ * operator may appear only once per batch and must not run other products
+ * while a launch of the batch is in flight.
+ * Errors: H2B_EINVAL (bad arguments, repeated operator), H2B_EDEVICE. */
+h2b_status h2b_batch_create(int nops, const h2b_op *ops, const int *trans, const double *alpha,
+                            const double *const *x, const int64_t *ldx, double *const *y,
+                            const int64_t *ldy, const int *nrhs, void *hip_stream, h2b_batch *out);
+h2b_status h2b_batch_launch(h2b_batch batch, void *hip_stream);
+h2b_status h2b_batch_destroy(h2b_batch batch);
+
+/* Autotuner for products with nrhs (2..64) right-hand sides: times the
+ * coupling product of this operator for block widths of 16, 32 and 64
+ * right-hand sides (and, for the F32/BF16 far field on matrix cores, two
+ * staging depths), keeps the fastest for later h2b_matvec calls with nrhs > 1,
+ * and allocates the block work vectors (so that later products allocate
+ * nothing).  best_us (may be NULL) receives the tuned coupling time in
+ * microseconds for nrhs columns.  Synchronises hip_stream.
+ * Errors: H2B_EINVAL for nrhs outside 2..64. */
+h2b_status h2b_op_tune(h2b_op op, int nrhs, void *hip_stream, double *best_us);
 
 /* Per-phase timing of the products on an operator, measured with HIP events on
  * each product's own stream.  h2b_op_set_timing(op, 1) starts recording (one

@@ -30,7 +30,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 H2B_OK, H2B_EINVAL, H2B_ENOMEM, H2B_EDEVICE, H2B_ESTATE, H2B_ENOTSUP = 0, -1, -2, -3, -4, -5
 H2B_P0, H2B_P1 = 0, 1
 H2B_SLP, H2B_DLP = 0, 1
-H2B_F64, H2B_F32 = 0, 1
+H2B_F64, H2B_F32, H2B_BF16 = 0, 1, 2
+_DTYPES = {"f64": H2B_F64, "f32": H2B_F32, "bf16": H2B_BF16}
 
 _i64, _i32, _dbl, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
 _P = ctypes.POINTER
@@ -69,6 +70,10 @@ _SIGS = {
     "h2b_op_destroy": ([_vp], ctypes.c_int),
     "h2b_op_info": ([_vp, _P(h2b_op_stats)], ctypes.c_int),
     "h2b_matvec": ([_vp, ctypes.c_int, _dbl, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
+    "h2b_op_tune": ([_vp, ctypes.c_int, _vp, _P(_dbl)], ctypes.c_int),
+    "h2b_batch_create": ([ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_vp)], ctypes.c_int),
+    "h2b_batch_launch": ([_vp, _vp], ctypes.c_int),
+    "h2b_batch_destroy": ([_vp], ctypes.c_int),
     "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
 }
@@ -196,7 +201,7 @@ class Operator:
         self.cols = self.rows if self.kernel == H2B_SLP else Tree(self.mesh, H2B_P1, leaf)
         self.blocks = Blocks(self.rows, self.cols, eta, far_disabled)
         p = default_params(order_m=order_m, q_near=q_near, recompress_tol=recompress_tol,
-                           farfield_dtype=H2B_F64 if farfield_dtype == "f64" else H2B_F32)
+                           farfield_dtype=_DTYPES[farfield_dtype])
         h = _vp()
         _check(h2b_assemble(self.blocks.handle, self.kernel, ctypes.byref(p), _stream_ptr(stream),
                             ctypes.byref(h)))
@@ -226,6 +231,12 @@ class Operator:
                           _vp(y.data_ptr()), ldy, nrhs, _stream_ptr(stream)))
         return y
 
+    def tune(self, nrhs, stream=None):
+        """Autotune the many-right-hand-side coupling product; returns its time in us."""
+        best = _dbl()
+        _check(h2b_op_tune(self.handle, int(nrhs), _stream_ptr(stream), ctypes.byref(best)))
+        return best.value
+
     def set_timing(self, on=True):
         _check(h2b_op_set_timing(self.handle, int(bool(on))))
 
@@ -235,6 +246,41 @@ class Operator:
         return dict(zip(("gather", "forward", "coupling", "backward", "nearfield", "scatter"), out))
 
     def __del__(self, _destroy=h2b_op_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Products of several operators captured into one HIP graph.
+
+    ``Batch([(op, x, y), ...], alpha=1.0, trans=False)`` binds the device
+    vectors; ``launch()`` replays y_i += alpha op_i x_i for all i."""
+
+    def __init__(self, items, alpha=1.0, trans=False, stream=None):
+        n = len(items)
+        for op, x, y in items:
+            nin = op.shape[0] if trans else op.shape[1]
+            nout = op.shape[1] if trans else op.shape[0]
+            if x.shape[0] != nin or y.shape[0] != nout:
+                raise ValueError("vector length does not match its operator")
+        self.items = list(items)  # keeps operators and vectors alive
+        ops = (_vp * n)(*[op.handle for op, _, _ in items])
+        tr = (ctypes.c_int * n)(*([int(bool(trans))] * n))
+        al = (_dbl * n)(*([float(alpha)] * n))
+        xs = (_vp * n)(*[x.data_ptr() for _, x, _ in items])
+        ys = (_vp * n)(*[y.data_ptr() for _, _, y in items])
+        ldx = (_i64 * n)(*[x.shape[0] if x.dim() == 1 else x.stride(1) for _, x, _ in items])
+        ldy = (_i64 * n)(*[y.shape[0] if y.dim() == 1 else y.stride(1) for _, _, y in items])
+        nr = (ctypes.c_int * n)(*[1 if x.dim() == 1 else x.shape[1] for _, x, _ in items])
+        h = _vp()
+        _check(h2b_batch_create(n, ops, tr, al, xs, ldx, ys, ldy, nr, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(h2b_batch_launch(self.handle, _stream_ptr(stream)))
+
+    def __del__(self, _destroy=h2b_batch_destroy):
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None

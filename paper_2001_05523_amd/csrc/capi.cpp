@@ -19,6 +19,9 @@ struct h2b_blocks_s {
 struct h2b_op_s {
     std::unique_ptr<h2b::Op> op;
 };
+struct h2b_batch_s {
+    std::unique_ptr<h2b::Batch> b;
+};
 
 namespace {
 
@@ -213,6 +216,46 @@ h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64
         need(op, "op");
         h2b::matvec(*op->op, trans ? 1 : 0, alpha, x, ldx, y, ldy, nrhs,
                     static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_batch_create(int nops, const h2b_op *ops, const int *trans, const double *alpha,
+                            const double *const *x, const int64_t *ldx, double *const *y,
+                            const int64_t *ldy, const int *nrhs, void *hip_stream, h2b_batch *out)
+{
+    return guarded([&] {
+        need(ops, "ops");
+        need(out, "out");
+        std::vector<h2b::Op *> raw(nops > 0 ? nops : 0);
+        for (int i = 0; i < nops; ++i) {
+            need(ops[i], "ops[i]");
+            raw[i] = ops[i]->op.get();
+        }
+        auto b = h2b::batch_create(nops, raw.data(), trans, alpha, x, ldx, y, ldy, nrhs,
+                                   static_cast<hipStream_t>(hip_stream));
+        *out = new h2b_batch_s{std::move(b)};
+    });
+}
+
+h2b_status h2b_batch_launch(h2b_batch batch, void *hip_stream)
+{
+    return guarded([&] {
+        need(batch, "batch");
+        h2b::batch_launch(*batch->b, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_batch_destroy(h2b_batch batch)
+{
+    delete batch;
+    return H2B_OK;
+}
+
+h2b_status h2b_op_tune(h2b_op op, int nrhs, void *hip_stream, double *best_us)
+{
+    return guarded([&] {
+        need(op, "op");
+        h2b::tune(*op->op, nrhs, static_cast<hipStream_t>(hip_stream), best_us);
     });
 }
 

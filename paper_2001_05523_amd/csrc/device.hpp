@@ -7,6 +7,8 @@
 
 namespace h2b {
 
+using bf16_t = __bf16;     // storage type of the BF16 coupling matrices
+
 constexpr int QMAX = 16;   // largest Gauss order per dimension
 constexpr int MMAX = 6;    // largest Chebyshev order per axis
 
@@ -70,6 +72,24 @@ void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const 
 
 // out = per-group transpose of the panels of rp (same offsets).
 template <typename T> void launch_transpose_panels(const RowPanels &rp, const T *in, T *out, hipStream_t st);
+
+// Many right-hand sides, vectors stored row-major per block of rb columns
+// (entry (i, r) at i * rb + r), rb in {16, 32, 64}.
+template <typename VT, typename XT, typename YT>
+void launch_rowpanel_mrhs(const RowPanels &rp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
+                          bool accumulate, hipStream_t st, Role role);
+// Coupling on matrix cores: FP32 or BF16 panels, FP32 vectors and accumulation,
+// kc = input columns staged per step (32 or 64).
+template <typename VT>
+void launch_rowpanel_mrhs_mfma(const RowPanels &rp, int g0, int g1, int rb, int kc, const VT *vals,
+                               const float *x, float *y, bool accumulate, hipStream_t st);
+template <typename VT, typename XT, typename YT>
+void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
+                          bool accumulate, hipStream_t st, Role role);
+void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const double *x, int64_t ldx,
+                        double *xp, hipStream_t st);
+void launch_scatter_mrhs(const int32_t *perm, int64_t n, int nb, int rb, double alpha, const double *yp,
+                         double *y, int64_t ldy, hipStream_t st);
 
 // xp[k + c*n] = x[perm[k] + c*ldx]
 void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,

@@ -444,6 +444,7 @@ __global__ __launch_bounds__(NT) void k_coupling(RowPanelDev d, const double *__
 
 template <typename T> struct Acc { using type = double; };
 template <> struct Acc<float> { using type = float; };
+template <> struct Acc<bf16_t> { using type = float; };
 
 template <typename A> __device__ inline A wave_sum(A v)
 {
@@ -884,6 +885,8 @@ template void launch_coupling<double>(const RowPanels &, const double *, const d
                                       hipStream_t);
 template void launch_coupling<float>(const RowPanels &, const double *, const double *, int, float *,
                                      hipStream_t);
+template void launch_coupling<bf16_t>(const RowPanels &, const double *, const double *, int, bf16_t *,
+                                      hipStream_t);
 template void launch_fill_zero<double>(double *, int64_t, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
 template void launch_transpose_panels<double>(const RowPanels &, const double *, double *, hipStream_t);
@@ -897,6 +900,7 @@ H2B_PANEL_INST(double, double, double)
 H2B_PANEL_INST(float, double, float)
 H2B_PANEL_INST(float, float, float)
 H2B_PANEL_INST(float, float, double)
+H2B_PANEL_INST(bf16_t, float, float)
 #undef H2B_PANEL_INST
 
 }  // namespace h2b

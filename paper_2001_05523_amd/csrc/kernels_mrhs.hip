@@ -1,0 +1,380 @@
+// Products with many right-hand sides (blocks of RB columns): the panel
+// products become small GEMMs.  Vectors are stored row-major per block, entry
+// (i, r) at i * RB + r, so that every input segment is a contiguous
+// seg_len x RB tile.
+//
+//   k_rowpanel_mrhs       Y[rows of g] (+)= P_g X[columns of g], FMA in FP64/FP32
+//   k_rowpanel_mrhs_mfma  the same on matrix cores: FP32 (16x16x4) or BF16
+//                         (16x16x32) inputs with FP32 accumulation
+//   k_colpanel_mrhs       transposed product over column panels
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device.hpp"
+
+namespace h2b {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> struct AccM { using type = double; };
+template <> struct AccM<float> { using type = float; };
+template <> struct AccM<bf16_t> { using type = float; };
+
+
+// Input row of panel column c: walks the group's segments (small count).
+__device__ inline int seg_row(const RowPanelDev &d, int s0, int s1, int c)
+{
+    int s = s0;
+    while (s + 1 < s1 && c >= d.seg_len[s]) {
+        c -= d.seg_len[s];
+        ++s;
+    }
+    return d.seg_in[s] + c;
+}
+
+// Thread (t) owns rows 4*(t/16) .. +3 (64 rows per pass) and RB/16 right-hand
+// sides starting at (t%16)*(RB/16).
+template <typename VT, typename XT, typename YT, int ROLE, int RB>
+__global__ __launch_bounds__(NT) void k_rowpanel_mrhs(RowPanelDev d, int g0, const VT *__restrict__ vals,
+                                                      const XT *__restrict__ x, YT *__restrict__ y,
+                                                      int accumulate)
+{
+    using A = typename AccM<VT>::type;
+    constexpr int KC = 32;
+    constexpr int CR = RB / 16;
+    __shared__ A Ps[64][KC + 1];
+    __shared__ A Xs[KC][RB];
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const int t = threadIdx.x;
+    const int rq = (t / 16) * 4, cq = (t % 16) * CR;
+    for (int r0 = 0; r0 < nr; r0 += 64) {
+        A acc[4][CR];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < CR; ++j) acc[i][j] = 0;
+        for (int c0 = 0; c0 < nc; c0 += KC) {
+            const int cl = min(KC, nc - c0);
+            for (int e = t; e < 64 * KC; e += NT) {
+                const int i = e / KC, k = e % KC;
+                Ps[i][k] = (r0 + i < nr && k < cl) ? (A)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : A(0);
+            }
+            for (int e = t; e < KC * RB; e += NT) {
+                const int k = e / RB, r = e % RB;
+                Xs[k][r] = (k < cl) ? (A)x[(int64_t)seg_row(d, s0, s1, c0 + k) * RB + r] : A(0);
+            }
+            __syncthreads();
+#pragma unroll 8
+            for (int k = 0; k < KC; ++k) {
+                A a[4], b[CR];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = Ps[rq + i][k];
+#pragma unroll
+                for (int j = 0; j < CR; ++j) b[j] = Xs[k][cq + j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < CR; ++j) acc[i][j] += a[i] * b[j];
+            }
+            __syncthreads();
+        }
+        const int ob = d.out_begin[g];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + rq + i;
+            if (row >= nr) continue;
+#pragma unroll
+            for (int j = 0; j < CR; ++j) {
+                YT *dst = y + (int64_t)(ob + row) * RB + cq + j;
+                *dst = accumulate ? (YT)((A)*dst + acc[i][j]) : (YT)acc[i][j];
+            }
+        }
+    }
+}
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mb8 __attribute__((ext_vector_type(8)));
+
+// Matrix-core version.  Wave w computes the 16x16 output tiles (row tile,
+// rhs tile) with index w, w+4, ... among the 4 x (RB/16) tiles of a 64-row
+// pass.  FP32: v_mfma_f32_16x16x4f32, lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  BF16: v_mfma_f32_16x16x32_bf16, lane l holds
+// A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16].  Both return D[4(l/16)+j][l%16].
+template <typename VT, int ROLE, int RB, int KC>
+__global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0, const VT *__restrict__ vals,
+                                                           const float *__restrict__ x, float *__restrict__ y,
+                                                           int accumulate)
+{
+    constexpr bool BF = std::is_same<VT, bf16_t>::value;
+    constexpr int KS = BF ? 32 : 4;  // k per instruction
+    static_assert(KC % KS == 0, "chunk must be a multiple of the instruction depth");
+    constexpr int TILES = 4 * (RB / 16);
+    constexpr int TPW = (TILES + 3) / 4;
+    using S = typename std::conditional<BF, bf16_t, float>::type;
+    __shared__ S As[64][KC + (BF ? 8 : 1)];
+    __shared__ S Bs[KC][RB + (BF ? 8 : 1)];
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane % 16, lk = lane / 16;
+    for (int r0 = 0; r0 < nr; r0 += 64) {
+        mf4 acc[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) acc[q] = mf4{0.f, 0.f, 0.f, 0.f};
+        for (int c0 = 0; c0 < nc; c0 += KC) {
+            const int cl = min(KC, nc - c0);
+            for (int e = t; e < 64 * KC; e += NT) {
+                const int i = e / KC, k = e % KC;
+                As[i][k] = (r0 + i < nr && k < cl) ? (S)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : (S)0.f;
+            }
+            for (int e = t; e < KC * RB; e += NT) {
+                const int k = e / RB, r = e % RB;
+                Bs[k][r] = (k < cl) ? (S)x[(int64_t)seg_row(d, s0, s1, c0 + k) * RB + r] : (S)0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tile = wave + 4 * q;
+                if (tile >= TILES) break;
+                const int ti = (tile % 4) * 16, tj = (tile / 4) * 16;
+                if (r0 + ti >= nr) continue;
+#pragma unroll
+                for (int k0 = 0; k0 < KC; k0 += KS) {
+                    if constexpr (BF) {
+                        mb8 a, b;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            a[e] = As[ti + li][k0 + 8 * lk + e];
+                            b[e] = Bs[k0 + 8 * lk + e][tj + li];
+                        }
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+                    } else {
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[ti + li][k0 + lk], Bs[k0 + lk][tj + li],
+                                                                      acc[q], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int ob = d.out_begin[g];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile >= TILES) break;
+            const int ti = (tile % 4) * 16, tj = (tile / 4) * 16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = r0 + ti + 4 * lk + j;
+                if (row >= nr) continue;
+                float *dst = y + (int64_t)(ob + row) * RB + tj + li;
+                *dst = accumulate ? *dst + acc[q][j] : acc[q][j];
+            }
+        }
+    }
+}
+
+// Transposed product: Y[ob + j][:] (+)= sum_b sum_i P_b[i][c0 + j] X[in_b + i][:],
+// 64 outputs rows per pass, rows of the blocks in chunks of KC staged in LDS.
+template <typename VT, typename XT, typename YT, int ROLE, int RB>
+__global__ __launch_bounds__(NT) void k_colpanel_mrhs(ColPanelDev d, int g0, const VT *__restrict__ vals,
+                                                      const XT *__restrict__ x, YT *__restrict__ y,
+                                                      int accumulate)
+{
+    using A = typename AccM<VT>::type;
+    constexpr int KC = 32;
+    constexpr int CR = RB / 16;
+    __shared__ A Ps[KC][64 + 1];
+    __shared__ A Xs[KC][RB];
+    const int g = g0 + blockIdx.x;
+    const int ob = d.out_begin[g], ol = d.out_len[g];
+    const int b0 = d.blk_ptr[g], b1 = d.blk_ptr[g + 1];
+    const int t = threadIdx.x;
+    const int jq = (t / 16) * 4, cq = (t % 16) * CR;
+    for (int j0 = 0; j0 < ol; j0 += 64) {
+        A acc[4][CR];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < CR; ++j) acc[i][j] = 0;
+        for (int b = b0; b < b1; ++b) {
+            const int nrb = d.b_nrows[b];
+            const int64_t stride = d.b_stride[b];
+            const VT *base = vals + d.b_val_off[b] + d.b_c0[b] + j0;
+            const XT *xin = x + (int64_t)d.b_in[b] * RB;
+            for (int i0 = 0; i0 < nrb; i0 += KC) {
+                const int il = min(KC, nrb - i0);
+                for (int e = t; e < KC * 64; e += NT) {
+                    const int i = e / 64, j = e % 64;
+                    Ps[i][j] = (i < il && j0 + j < ol) ? (A)base[(int64_t)(i0 + i) * stride + j] : A(0);
+                }
+                for (int e = t; e < KC * RB; e += NT) {
+                    const int i = e / RB, r = e % RB;
+                    Xs[i][r] = (i < il) ? (A)xin[(int64_t)(i0 + i) * RB + r] : A(0);
+                }
+                __syncthreads();
+#pragma unroll 8
+                for (int i = 0; i < KC; ++i) {
+                    A a[4], bb[CR];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a[q] = Ps[i][jq + q];
+#pragma unroll
+                    for (int q = 0; q < CR; ++q) bb[q] = Xs[i][cq + q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int p = 0; p < CR; ++p) acc[q][p] += a[q] * bb[p];
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + jq + q;
+            if (j >= ol) continue;
+#pragma unroll
+            for (int p = 0; p < CR; ++p) {
+                YT *dst = y + (int64_t)(ob + j) * RB + cq + p;
+                *dst = accumulate ? (YT)((A)*dst + acc[q][p]) : (YT)acc[q][p];
+            }
+        }
+    }
+}
+
+__global__ void k_gather_mrhs(const int32_t *__restrict__ perm, int64_t n, int nb, int rb,
+                              const double *__restrict__ x, int64_t ldx, double *__restrict__ xp)
+{
+    const int64_t tot = n * rb;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / rb;
+        const int r = (int)(e % rb);
+        xp[e] = (r < nb) ? x[perm[k] + r * ldx] : 0.0;
+    }
+}
+
+__global__ void k_scatter_mrhs(const int32_t *__restrict__ perm, int64_t n, int nb, int rb, double alpha,
+                               const double *__restrict__ yp, double *__restrict__ y, int64_t ldy)
+{
+    const int64_t tot = n * nb;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e % n;
+        const int r = (int)(e / n);
+        y[perm[k] + r * ldy] += alpha * yp[k * rb + r];
+    }
+}
+
+inline int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + NT - 1) / NT, 1), 1 << 20); }
+
+}  // namespace
+
+template <typename VT, typename XT, typename YT>
+void launch_rowpanel_mrhs(const RowPanels &rp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
+                          bool accumulate, hipStream_t st, Role role)
+{
+    if (g1 <= g0) return;
+    const int acc = accumulate ? 1 : 0;
+#define H2B_RP(R, RBV)                                                                                       \
+    hipLaunchKernelGGL((k_rowpanel_mrhs<VT, XT, YT, R, RBV>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, \
+                       x, y, acc)
+#define H2B_RP_RB(R)                                                                                         \
+    if (rb == 16) H2B_RP(R, 16);                                                                             \
+    else if (rb == 32) H2B_RP(R, 32);                                                                        \
+    else H2B_RP(R, 64);
+    switch (role) {
+    case Role::Leaf: H2B_RP_RB(0) break;
+    case Role::Transfer: H2B_RP_RB(1) break;
+    case Role::Coupling: H2B_RP_RB(2) break;
+    default: H2B_RP_RB(3) break;
+    }
+#undef H2B_RP_RB
+#undef H2B_RP
+    hip_check(hipGetLastError(), "row panel (multi-rhs) launch");
+}
+
+template <typename VT>
+void launch_rowpanel_mrhs_mfma(const RowPanels &rp, int g0, int g1, int rb, int kc, const VT *vals,
+                               const float *x, float *y, bool accumulate, hipStream_t st)
+{
+    if (g1 <= g0) return;
+    const int acc = accumulate ? 1 : 0;
+#define H2B_MF(RBV, KCV)                                                                                      \
+    hipLaunchKernelGGL((k_rowpanel_mrhs_mfma<VT, 2, RBV, KCV>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0,   \
+                       vals, x, y, acc)
+    if (kc <= 32) {
+        if (rb == 16) H2B_MF(16, 32);
+        else if (rb == 32) H2B_MF(32, 32);
+        else H2B_MF(64, 32);
+    } else {
+        if (rb == 16) H2B_MF(16, 64);
+        else if (rb == 32) H2B_MF(32, 64);
+        else H2B_MF(64, 64);
+    }
+#undef H2B_MF
+    hip_check(hipGetLastError(), "row panel (matrix core) launch");
+}
+
+template <typename VT, typename XT, typename YT>
+void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
+                          bool accumulate, hipStream_t st, Role role)
+{
+    if (g1 <= g0) return;
+    const int acc = accumulate ? 1 : 0;
+#define H2B_CP(R, RBV)                                                                                       \
+    hipLaunchKernelGGL((k_colpanel_mrhs<VT, XT, YT, R, RBV>), dim3(g1 - g0), dim3(NT), 0, st, cp.dev, g0, vals, \
+                       x, y, acc)
+#define H2B_CP_RB(R)                                                                                         \
+    if (rb == 16) H2B_CP(R, 16);                                                                             \
+    else if (rb == 32) H2B_CP(R, 32);                                                                        \
+    else H2B_CP(R, 64);
+    switch (role) {
+    case Role::Leaf: H2B_CP_RB(0) break;
+    case Role::Transfer: H2B_CP_RB(1) break;
+    case Role::Coupling: H2B_CP_RB(2) break;
+    default: H2B_CP_RB(3) break;
+    }
+#undef H2B_CP_RB
+#undef H2B_CP
+    hip_check(hipGetLastError(), "column panel (multi-rhs) launch");
+}
+
+void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const double *x, int64_t ldx,
+                        double *xp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_mrhs, dim3(grid_for(n * rb)), dim3(NT), 0, st, perm, n, nb, rb, x, ldx, xp);
+    hip_check(hipGetLastError(), "gather launch");
+}
+
+void launch_scatter_mrhs(const int32_t *perm, int64_t n, int nb, int rb, double alpha, const double *yp,
+                         double *y, int64_t ldy, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_mrhs, dim3(grid_for(n * nb)), dim3(NT), 0, st, perm, n, nb, rb, alpha, yp, y,
+                       ldy);
+    hip_check(hipGetLastError(), "scatter launch");
+}
+
+#define H2B_MRHS_INST(VT, XT, YT)                                                                           \
+    template void launch_rowpanel_mrhs<VT, XT, YT>(const RowPanels &, int, int, int, const VT *, const XT *, \
+                                                   YT *, bool, hipStream_t, Role);                          \
+    template void launch_colpanel_mrhs<VT, XT, YT>(const ColPanels &, int, int, int, const VT *, const XT *, \
+                                                   YT *, bool, hipStream_t, Role);
+H2B_MRHS_INST(double, double, double)
+H2B_MRHS_INST(float, double, float)
+H2B_MRHS_INST(float, float, float)
+H2B_MRHS_INST(float, float, double)
+H2B_MRHS_INST(bf16_t, float, float)
+#undef H2B_MRHS_INST
+template void launch_rowpanel_mrhs_mfma<float>(const RowPanels &, int, int, int, int, const float *, const float *,
+                                               float *, bool, hipStream_t);
+template void launch_rowpanel_mrhs_mfma<bf16_t>(const RowPanels &, int, int, int, int, const bf16_t *,
+                                                const float *, float *, bool, hipStream_t);
+
+}  // namespace h2b

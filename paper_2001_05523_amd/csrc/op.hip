@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <type_traits>
 
 #include "device.hpp"
 #include "op.hpp"
@@ -193,8 +194,8 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
 {
     if (p.order_m < 1 || p.order_m > MMAX) fail(H2B_EINVAL, "order_m must be in 1..6");
     if (p.q_near < 2 || p.q_near > QMAX) fail(H2B_EINVAL, "q_near must be in 2..16");
-    if (p.farfield_dtype != H2B_F64 && p.farfield_dtype != H2B_F32)
-        fail(H2B_EINVAL, "farfield_dtype must be H2B_F64 or H2B_F32");
+    if (p.farfield_dtype != H2B_F64 && p.farfield_dtype != H2B_F32 && p.farfield_dtype != H2B_BF16)
+        fail(H2B_EINVAL, "farfield_dtype must be H2B_F64, H2B_F32 or H2B_BF16");
     if (!(p.recompress_tol >= 0.0)) fail(H2B_EINVAL, "recompress_tol must be >= 0");
     if (kernel == H2B_SLP && blocks->cols->space != H2B_P0)
         fail(H2B_EINVAL, "the single-layer matrix needs a P0 column tree");
@@ -300,8 +301,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     // with recompression the interpolation operator is built in FP64 first
     const bool rc = p.recompress_tol > 0.0;
     const h2b_dtype adt = rc ? H2B_F64 : p.farfield_dtype;
-    const size_t fsz = (adt == H2B_F64) ? sizeof(double) : sizeof(float);
-    op->cpl_vals.alloc(fsz * std::max<int64_t>(op->cpl.total, 1));
+    op->cpl_vals.alloc(coupling_size(adt) * std::max<int64_t>(op->cpl.total, 1));
     for (Basis *B : bases) {
         if (adt == H2B_F64)
             assemble_basis<double>(*B, m, B->axes, op->geo, st);
@@ -309,17 +309,18 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
             assemble_basis<float>(*B, m, B->axes, op->geo, st);
         transpose_basis_values(*B, adt, st);
     }
+    const double *rax = op->rowb->axes.as<double>(), *cax = op->colb->axes.as<double>();
     if (adt == H2B_F64)
-        launch_coupling<double>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
-                                op->cpl_vals.as<double>(), st);
+        launch_coupling<double>(op->cpl, rax, cax, m, op->cpl_vals.as<double>(), st);
+    else if (adt == H2B_F32)
+        launch_coupling<float>(op->cpl, rax, cax, m, op->cpl_vals.as<float>(), st);
     else
-        launch_coupling<float>(op->cpl, op->rowb->axes.as<double>(), op->colb->axes.as<double>(), m,
-                               op->cpl_vals.as<float>(), st);
+        launch_coupling<bf16_t>(op->cpl, rax, cax, m, op->cpl_vals.as<bf16_t>(), st);
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
 
     // work vectors
-    const size_t wsz = (p.farfield_dtype == H2B_F64) ? sizeof(double) : sizeof(float);
+    const size_t wsz = basis_size(p.farfield_dtype);
     const int64_t nmax = std::max(op->nrows, op->ncols);
     const int64_t hmax = std::max(op->rowb->hat_total, op->colb->hat_total);
     op->xp.alloc(sizeof(double) * nmax);
@@ -330,6 +331,9 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
 }
 
 // --------------------------------------------------------------- product
+//
+// F: type of the bases and of the cluster coefficients (double for F64, float
+// otherwise); C: storage type of the coupling matrices (double, float, bf16).
 
 template <typename F>
 static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
@@ -354,7 +358,20 @@ static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 // Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
 // [4] after backward, [5] after nearfield, [6] after scatter.  The coupling and
 // nearfield phases each bracket exactly one kernel launch.
-template <typename F>
+static hipEvent_t *event_set(Op &op, hipStream_t st)
+{
+    if (!op.timing) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return nullptr;
+    if (op.nev == op.ev.size()) {
+        std::array<hipEvent_t, 7> set{};
+        for (auto &e : set) hip_check(hipEventCreate(&e), "event create");
+        op.ev.push_back(set);
+    }
+    return op.ev[op.nev++].data();
+}
+
+template <typename F, typename C>
 static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
 {
     const Basis &Bin = trans ? *op.rowb : *op.colb;
@@ -363,15 +380,7 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     const int64_t nout = trans ? op.ncols : op.nrows;
     double *xp = op.xp.as<double>(), *yp = op.yp.as<double>();
     F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
-    hipEvent_t *ev = nullptr;
-    if (op.timing) {
-        if (op.nev == op.ev.size()) {
-            std::array<hipEvent_t, 7> set{};
-            for (auto &e : set) hip_check(hipEventCreate(&e), "event create");
-            op.ev.push_back(set);
-        }
-        ev = op.ev[op.nev++].data();
-    }
+    hipEvent_t *ev = event_set(op, st);
     auto mark = [&](int i) {
         if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
     };
@@ -383,10 +392,10 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     forward<F>(Bin, xp, xhat, st);
     mark(2);
     if (!trans)
-        launch_rowpanel<F, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, true, st,
+        launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, true, st,
                                  Role::Coupling);
     else
-        launch_colpanel<F, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<F>(), xhat, yhat, st,
+        launch_colpanel<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, st,
                                  Role::Coupling);
     mark(3);
     backward<F>(Bout, yhat, yp, st);
@@ -402,8 +411,97 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     mark(6);
 }
 
-void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
-            int nrhs, hipStream_t st)
+// ------------------------------------------------ many right-hand sides
+
+static void ensure_block_buffers(Op &op, int rb)
+{
+    if (op.mrhs_rb >= rb) return;
+    const int64_t nmax = std::max(op.nrows, op.ncols);
+    const int64_t hmax = std::max<int64_t>(std::max(op.rowb->hat_total, op.colb->hat_total), 1);
+    const size_t fsz = basis_size(op.params.farfield_dtype);
+    op.xpb.alloc(sizeof(double) * nmax * rb);
+    op.ypb.alloc(sizeof(double) * nmax * rb);
+    op.xhatb.alloc(fsz * hmax * rb);
+    op.yhatb.alloc(fsz * hmax * rb);
+    op.mrhs_rb = rb;
+}
+
+template <typename F, typename C>
+static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *yhat, hipStream_t st)
+{
+    if (trans) {
+        launch_colpanel_mrhs<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), rb, op.cpl_vals.as<C>(), xhat, yhat, true,
+                                      st, Role::Coupling);
+    } else if constexpr (std::is_same<F, float>::value) {
+        launch_rowpanel_mrhs_mfma<C>(op.cpl, 0, op.cpl.ngroups(), rb, kc, op.cpl_vals.as<C>(), xhat, yhat, true,
+                                     st);
+    } else {
+        launch_rowpanel_mrhs<C, F, F>(op.cpl, 0, op.cpl.ngroups(), rb, op.cpl_vals.as<C>(), xhat, yhat, true, st,
+                                      Role::Coupling);
+    }
+}
+
+// Product for nb <= rb right-hand sides at once (block vectors row-major).
+template <typename F, typename C>
+static void product_block(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y,
+                          int64_t ldy, int nb, int rb, hipStream_t st)
+{
+    const Basis &Bin = trans ? *op.rowb : *op.colb;
+    const Basis &Bout = trans ? *op.colb : *op.rowb;
+    const int64_t nin = trans ? op.nrows : op.ncols;
+    const int64_t nout = trans ? op.ncols : op.nrows;
+    double *xp = op.xpb.as<double>(), *yp = op.ypb.as<double>();
+    F *xhat = op.xhatb.as<F>(), *yhat = op.yhatb.as<F>();
+    hipEvent_t *ev = event_set(op, st);
+    auto mark = [&](int i) {
+        if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
+    };
+    launch_fill_zero<F>(yhat, Bout.hat_total * rb, st);
+    launch_fill_zero<double>(yp, nout * rb, st);
+    mark(0);
+    launch_gather_mrhs(Bin.perm_dev, nin, nb, rb, x, ldx, xp, st);
+    mark(1);
+    launch_colpanel_mrhs<F, double, F>(Bin.leaf_F, 0, Bin.leaf_F.ngroups(), rb, Bin.leafT_vals.as<F>(), xp, xhat,
+                                       false, st, Role::Leaf);
+    for (auto &s : Bin.fw_steps)
+        launch_colpanel_mrhs<F, F, F>(Bin.trans_F, s.first, s.second, rb, Bin.transT_vals.as<F>(), xhat, xhat,
+                                      false, st, Role::Transfer);
+    mark(2);
+    coupling_block<F, C>(op, trans, rb, op.tune_kc, xhat, yhat, st);
+    mark(3);
+    for (auto &s : Bout.bw_steps)
+        launch_colpanel_mrhs<F, F, F>(Bout.trans_T, s.first, s.second, rb, Bout.trans_vals.as<F>(), yhat, yhat,
+                                      true, st, Role::Transfer);
+    launch_colpanel_mrhs<F, F, double>(Bout.leaf_T, 0, Bout.leaf_T.ngroups(), rb, Bout.leaf_vals.as<F>(), yhat,
+                                       yp, true, st, Role::Leaf);
+    mark(4);
+    if (!trans)
+        launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb, op.near_vals.as<double>(),
+                                                     xp, yp, true, st, Role::Near);
+    else
+        launch_colpanel_mrhs<double, double, double>(op.near_T, 0, op.near_T.ngroups(), rb,
+                                                     op.near_vals.as<double>(), xp, yp, true, st, Role::Near);
+    mark(5);
+    launch_scatter_mrhs(Bout.perm_dev, nout, nb, rb, alpha, yp, y, ldy, st);
+    mark(6);
+}
+
+template <typename F, typename C>
+static void product(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+                    int nrhs, hipStream_t st)
+{
+    if (nrhs == 1) {
+        product_one<F, C>(op, trans, alpha, x, y, st);
+        return;
+    }
+    const int rb = op.tune_rb > 0 ? op.tune_rb : std::min(64, (nrhs + 15) / 16 * 16);
+    ensure_block_buffers(op, rb);
+    for (int c = 0; c < nrhs; c += rb)
+        product_block<F, C>(op, trans, alpha, x + c * ldx, ldx, y + c * ldy, ldy, std::min(rb, nrhs - c), rb, st);
+}
+
+void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
+                        int nrhs)
 {
     const int64_t nin = trans ? op.nrows : op.ncols;
     const int64_t nout = trans ? op.ncols : op.nrows;
@@ -417,11 +515,75 @@ void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, doubl
         const char *ye = yb + sizeof(double) * (size_t)(ldy * (nrhs - 1) + nout);
         if (xb < ye && yb < xe) fail(H2B_EINVAL, "x and y overlap");
     }
-    for (int c = 0; c < nrhs; ++c) {
-        if (op.params.farfield_dtype == H2B_F64)
-            product_one<double>(op, trans, alpha, x + c * ldx, y + c * ldy, st);
+}
+
+void prepare_product(Op &op, int nrhs)
+{
+    if (nrhs > 1) ensure_block_buffers(op, op.tune_rb > 0 ? op.tune_rb : std::min(64, (nrhs + 15) / 16 * 16));
+}
+
+void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+            int nrhs, hipStream_t st)
+{
+    check_product_args(op, trans, x, ldx, y, ldy, nrhs);
+    switch (op.params.farfield_dtype) {
+    case H2B_F64: product<double, double>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
+    case H2B_F32: product<float, float>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
+    default: product<float, bf16_t>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
+    }
+}
+
+// Autotuner of the many-right-hand-side coupling product: times every block
+// width rb in {16, 32, 64} (and, on matrix cores, staging depth kc in {32, 64})
+// on the operator's own coupling panels and keeps the fastest per column.
+template <typename F, typename C>
+static void tune_impl(Op &op, int nrhs, hipStream_t st, double *best_us)
+{
+    std::vector<std::pair<int, int>> cand;
+    for (int rb : {16, 32, 64}) {
+        if (rb > std::max(16, (nrhs + 15) / 16 * 16)) continue;
+        if (std::is_same<F, float>::value)
+            for (int kc : {32, 64}) cand.push_back({rb, kc});
         else
-            product_one<float>(op, trans, alpha, x + c * ldx, y + c * ldy, st);
+            cand.push_back({rb, 32});
+    }
+    ensure_block_buffers(op, 64);
+    F *xh = op.xhatb.as<F>(), *yh = op.yhatb.as<F>();
+    const int64_t hmax = std::max(op.rowb->hat_total, op.colb->hat_total);
+    launch_fill_zero<F>(xh, hmax * 64, st);
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    double best = 1e300;
+    for (auto &c : cand) {
+        coupling_block<F, C>(op, 0, c.first, c.second, xh, yh, st);  // warm-up
+        hip_check(hipEventRecord(e0, st), "event");
+        for (int rep = 0; rep < 3; ++rep) coupling_block<F, C>(op, 0, c.first, c.second, xh, yh, st);
+        hip_check(hipEventRecord(e1, st), "event");
+        hip_check(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+        // time per right-hand side for nrhs columns processed in blocks of rb
+        const int blocks = (nrhs + c.first - 1) / c.first;
+        const double t = ms / 3.0 * blocks;
+        if (t < best) {
+            best = t;
+            op.tune_rb = c.first;
+            op.tune_kc = c.second;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_us) *best_us = best * 1e3;
+}
+
+void tune(Op &op, int nrhs, hipStream_t st, double *best_us)
+{
+    if (nrhs < 2 || nrhs > 64) fail(H2B_EINVAL, "nrhs must be in 2..64");
+    switch (op.params.farfield_dtype) {
+    case H2B_F64: tune_impl<double, double>(op, nrhs, st, best_us); break;
+    case H2B_F32: tune_impl<float, float>(op, nrhs, st, best_us); break;
+    default: tune_impl<float, bf16_t>(op, nrhs, st, best_us); break;
     }
 }
 
@@ -451,9 +613,9 @@ void op_stats(const Op &op, h2b_op_stats &s)
     s.coupling_entries = op.cpl.total;
     s.row_basis_entries = op.rowb->leaf.total + op.rowb->trans.total;
     s.col_basis_entries = (op.colb == op.rowb) ? 0 : op.colb->leaf.total + op.colb->trans.total;
-    const int64_t fsz = (op.params.farfield_dtype == H2B_F64) ? 8 : 4;
     s.bytes_near = op.near.total * 8;
-    s.bytes_far = (s.coupling_entries + s.row_basis_entries + s.col_basis_entries) * fsz;
+    s.bytes_far = s.coupling_entries * (int64_t)coupling_size(op.params.farfield_dtype) +
+                  (s.row_basis_entries + s.col_basis_entries) * (int64_t)basis_size(op.params.farfield_dtype);
     s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.xhat.bytes + op.yhat.bytes);
     s.row_coeffs = op.rowb->hat_total;
     s.col_coeffs = op.colb->hat_total;

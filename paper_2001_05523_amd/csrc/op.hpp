@@ -51,11 +51,21 @@ struct Op {
     ColPanels cpl_T;
     DevMem cpl_vals;
     DevMem xp, yp, xhat, yhat;              // product work vectors
+    DevMem xpb, ypb, xhatb, yhatb;          // block work vectors (many right-hand sides)
+    int mrhs_rb = 0;                        // block width the block vectors are sized for
+    int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)
     bool timing = false;
     std::vector<std::array<hipEvent_t, 7>> ev;  // one event set per timed product
     size_t nev = 0;                              // timed products since timing was enabled
     ~Op();
 };
+
+// Element sizes of the far-field storage for a far-field dtype.
+inline size_t basis_size(h2b_dtype dt) { return dt == H2B_F64 ? sizeof(double) : sizeof(float); }
+inline size_t coupling_size(h2b_dtype dt)
+{
+    return dt == H2B_F64 ? sizeof(double) : dt == H2B_F32 ? sizeof(float) : sizeof(bf16_t);
+}
 
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
@@ -63,9 +73,27 @@ void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t 
 // Transposed copies of the leaf and transfer values (after they are final).
 void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
+void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
+                        int nrhs);
+// Allocates what a product with nrhs right-hand sides needs (before a capture).
+void prepare_product(Op &op, int nrhs);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);
+
+// A captured batch of products (one graph, one forked stream per operator).
+struct Batch {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Batch();
+};
+std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, const double *alpha,
+                                    const double *const *x, const int64_t *ldx, double *const *y,
+                                    const int64_t *ldy, const int *nrhs, hipStream_t st);
+void batch_launch(Batch &b, hipStream_t st);
 void phase_times(Op &op, double out[6]);
+void tune(Op &op, int nrhs, hipStream_t st, double *best_us);
 void op_stats(const Op &op, h2b_op_stats &s);
 
 }  // namespace h2b

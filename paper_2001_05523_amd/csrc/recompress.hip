@@ -594,15 +594,15 @@ void recompress_op(Op &op, double tol, hipStream_t st)
     DevMem Br, Bro, Bc, Bco;
     upload_blocks(orow.B, Br, Bro, st);
     if (!shared) upload_blocks(ocol.B, Bc, Bco, st);
-    const size_t fsz = (op.params.farfield_dtype == H2B_F64) ? sizeof(double) : sizeof(float);
     DevMem snew;
-    snew.alloc(fsz * std::max<int64_t>(cplN.total, 1));
+    snew.alloc(coupling_size(op.params.farfield_dtype) * std::max<int64_t>(cplN.total, 1));
+    const DevMem &BcU = shared ? Br : Bc, &BcoU = shared ? Bro : Bco;
     if (op.params.farfield_dtype == H2B_F64)
-        run_sandwich<double>(sw2, stil.as<double>(), snew.as<double>(), Br, Bro, shared ? Br : Bc,
-                             shared ? Bro : Bco, st);
+        run_sandwich<double>(sw2, stil.as<double>(), snew.as<double>(), Br, Bro, BcU, BcoU, st);
+    else if (op.params.farfield_dtype == H2B_F32)
+        run_sandwich<float>(sw2, stil.as<double>(), snew.as<float>(), Br, Bro, BcU, BcoU, st);
     else
-        run_sandwich<float>(sw2, stil.as<double>(), snew.as<float>(), Br, Bro, shared ? Br : Bc,
-                            shared ? Bro : Bco, st);
+        run_sandwich<bf16_t>(sw2, stil.as<double>(), snew.as<bf16_t>(), Br, Bro, BcU, BcoU, st);
     hip_check(hipStreamSynchronize(st), "coupling projection");
     op.cpl = std::move(cplN);
     op.cpl_T = ColPanels();

@@ -182,7 +182,7 @@ def test_multiple_right_hand_sides():
     torch.cuda.synchronize()
     for c in range(3):
         y1 = _run(op, X[:, c].cpu().numpy(), alpha=2.0)
-        np.testing.assert_array_equal(Y[:, c].cpu().numpy(), y1)
+        np.testing.assert_allclose(Y[:, c].cpu().numpy(), y1, rtol=0, atol=1e-13 * np.abs(y1).max())
 
 
 def test_argument_errors_leave_y_untouched():
@@ -215,3 +215,105 @@ def test_single_hip_runtime_loaded():
     libs = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
     assert len(libs) == 1, libs
     assert any("libh2bem.so" in ln for ln in maps)
+
+
+def _run_block(op, X, trans=False, alpha=1.0):
+    """X: (n, nrhs) numpy array; returns op(A) X through one block product."""
+    torch = _torch()
+    nout = op.shape[1] if trans else op.shape[0]
+    Xd = torch.tensor(np.asfortranarray(X), device="cuda").t().contiguous().t()
+    Yd = torch.zeros((X.shape[1], nout), dtype=torch.float64, device="cuda").t()
+    op.matvec(Xd, Yd, alpha=alpha, trans=trans)
+    torch.cuda.synchronize()
+    return Yd.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [64, 37])
+def test_many_right_hand_sides(dtype, nrhs):
+    """Blocks of right-hand sides (GEMM form, matrix cores for the FP32/BF16
+    coupling) agree with the single-vector products of the same operator:
+    FP64 to rounding, FP32 to 1e-5, BF16 within its 8-bit mantissa."""
+    h = _lib()
+    v, t = synth.octa_sphere(16)
+    for kernel in ("slp", "dlp"):
+        op = h.Operator(v, t, kernel=kernel, leaf=16, order_m=3, q_near=4, farfield_dtype=dtype)
+        ref_op = op if dtype == "f64" else h.Operator(v, t, kernel=kernel, leaf=16, order_m=3, q_near=4)
+        for trans in (False, True):
+            nin = op.shape[0] if trans else op.shape[1]
+            X = synth.random_vector(nin, 301, cols=nrhs)
+            Y = _run_block(op, X, trans=trans, alpha=0.5)
+            for c in (0, nrhs // 2, nrhs - 1):
+                y1 = _run(ref_op, X[:, c], trans=trans, alpha=0.5)
+                d = np.linalg.norm(Y[:, c] - y1) / np.linalg.norm(y1)
+                bound = {"f64": 1e-12, "f32": 1e-5, "bf16": 5e-3}[dtype]
+                assert d <= bound, (kernel, trans, c, d)
+
+
+def test_tuner_picks_a_tile_and_products_stay_exact():
+    h = _lib()
+    v, t = synth.octa_sphere(16)
+    op = h.Operator(v, t, kernel="slp", leaf=16, order_m=4, q_near=4, farfield_dtype="f32",
+                    recompress_tol=1e-6)
+    us = op.tune(64)
+    assert us > 0
+    X = synth.random_vector(op.shape[1], 303, cols=64)
+    Y = _run_block(op, X)
+    for c in (0, 63):
+        y1 = _run(op, X[:, c])
+        assert np.linalg.norm(Y[:, c] - y1) / np.linalg.norm(y1) <= 1e-5
+
+
+def test_batched_graph_of_uneven_meshes():
+    """Sixteen meshes of uneven size (spheres of random radius and ellipsoids
+    with random semi-axes, 2 s^2 ... triangles) captured into one graph: every
+    replay equals the eager products, with eager work and synchronisations
+    between replays."""
+    torch = _torch()
+    h = _lib()
+    rng = np.random.default_rng(302)
+    ops, xs, ys, refs = [], [], [], []
+    for k in range(16):
+        s = int(rng.integers(4, 13))
+        if k % 2 == 0:
+            r = rng.uniform(0.5, 2.0)
+            v, t = synth.ellipsoid(s, r, r, r)
+        else:
+            a, b, c = rng.uniform(0.5, 2.0, size=3)
+            v, t = synth.ellipsoid(s, a, b, c)
+        kern = "slp" if k % 3 else "dlp"
+        op = h.Operator(v, t, kernel=kern, leaf=16, order_m=3, q_near=4, farfield_dtype="f32")
+        x = torch.tensor(synth.random_vector(op.shape[1], 303 + k), device="cuda")
+        y = torch.zeros(op.shape[0], dtype=torch.float64, device="cuda")
+        ref = torch.zeros_like(y)
+        op.matvec(x, ref)
+        ops.append(op)
+        xs.append(x)
+        ys.append(y)
+        refs.append(ref)
+    torch.cuda.synchronize()
+    batch = h.Batch(list(zip(ops, xs, ys)))
+    for rep in range(4):
+        for y in ys:
+            y.zero_()
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        for y, ref in zip(ys, refs):
+            np.testing.assert_allclose(y.cpu().numpy(), ref.cpu().numpy(), rtol=0,
+                                       atol=1e-12 * float(ref.abs().max()))
+        # eager work in between replays
+        ops[0].matvec(xs[0], refs[0], alpha=0.0)
+        torch.cuda.synchronize()
+
+
+def test_batch_rejects_repeated_operator():
+    torch = _torch()
+    h = _lib()
+    v, t = synth.octa_sphere(4)
+    op = h.Operator(v, t, kernel="slp", leaf=8, order_m=2)
+    x = torch.ones(len(t), dtype=torch.float64, device="cuda")
+    y1 = torch.zeros_like(x)
+    y2 = torch.zeros_like(x)
+    with pytest.raises(h.H2BError):
+        h.Batch([(op, x, y1), (op, x, y2)])
