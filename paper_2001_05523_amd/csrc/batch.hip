@@ -34,30 +34,32 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
         check_product_args(*ops[i], trans[i], x[i], ldx[i], y[i], ldy[i], nrhs[i]);
         prepare_product(*ops[i], nrhs[i]);
     }
+    // the caller's stream may be the null stream, which cannot be captured:
+    // capture on a private origin stream (streams[nops]) and launch the graph
+    // on the caller's stream later
+    (void)st;
     auto b = std::make_unique<Batch>();
-    b->streams.resize(nops, nullptr);
+    b->streams.resize(nops + 1, nullptr);
     b->events.resize(nops + 1, nullptr);
-    for (int i = 0; i < nops; ++i)
-        hip_check(hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking), "stream create");
+    for (auto &s : b->streams) hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream create");
     for (auto &e : b->events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
-    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t err = hipSuccess;
+    hipStream_t origin = b->streams[nops];
+    hip_check(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal), "begin capture");
     try {
-        hip_check(hipEventRecord(b->events[nops], st), "fork");
+        hip_check(hipEventRecord(b->events[nops], origin), "fork");
         for (int i = 0; i < nops; ++i) {
             hip_check(hipStreamWaitEvent(b->streams[i], b->events[nops], 0), "fork");
             matvec(*ops[i], trans[i], alpha[i], x[i], ldx[i], y[i], ldy[i], nrhs[i], b->streams[i]);
             hip_check(hipEventRecord(b->events[i], b->streams[i]), "join");
-            hip_check(hipStreamWaitEvent(st, b->events[i], 0), "join");
+            hip_check(hipStreamWaitEvent(origin, b->events[i], 0), "join");
         }
     } catch (...) {
         hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(st, &g);
+        (void)hipStreamEndCapture(origin, &g);
         if (g) (void)hipGraphDestroy(g);
         throw;
     }
-    err = hipStreamEndCapture(st, &b->graph);
-    hip_check(err, "end capture");
+    hip_check(hipStreamEndCapture(origin, &b->graph), "end capture");
     hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
     return b;
 }

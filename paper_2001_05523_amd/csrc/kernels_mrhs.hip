@@ -272,6 +272,11 @@ __global__ void k_scatter_mrhs(const int32_t *__restrict__ perm, int64_t n, int 
     }
 }
 
+inline void check_rb(int rb)
+{
+    if (rb != 16 && rb != 32 && rb != 64) fail(H2B_EINVAL, "block width must be 16, 32 or 64");
+}
+
 inline int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + NT - 1) / NT, 1), 1 << 20); }
 
 }  // namespace
@@ -280,6 +285,7 @@ template <typename VT, typename XT, typename YT>
 void launch_rowpanel_mrhs(const RowPanels &rp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
                           bool accumulate, hipStream_t st, Role role)
 {
+    check_rb(rb);
     if (g1 <= g0) return;
     const int acc = accumulate ? 1 : 0;
 #define H2B_RP(R, RBV)                                                                                       \
@@ -304,6 +310,8 @@ template <typename VT>
 void launch_rowpanel_mrhs_mfma(const RowPanels &rp, int g0, int g1, int rb, int kc, const VT *vals,
                                const float *x, float *y, bool accumulate, hipStream_t st)
 {
+    check_rb(rb);
+    if (kc != 32 && kc != 64) fail(H2B_EINVAL, "staging depth must be 32 or 64");
     if (g1 <= g0) return;
     const int acc = accumulate ? 1 : 0;
 #define H2B_MF(RBV, KCV)                                                                                      \
@@ -326,6 +334,7 @@ template <typename VT, typename XT, typename YT>
 void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
                           bool accumulate, hipStream_t st, Role role)
 {
+    check_rb(rb);
     if (g1 <= g0) return;
     const int acc = accumulate ? 1 : 0;
 #define H2B_CP(R, RBV)                                                                                       \
@@ -349,6 +358,8 @@ void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT 
 void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const double *x, int64_t ldx,
                         double *xp, hipStream_t st)
 {
+    check_rb(rb);
+    if (nb < 1 || nb > rb) fail(H2B_EINVAL, "block holds 1..rb right-hand sides");
     hipLaunchKernelGGL(k_gather_mrhs, dim3(grid_for(n * rb)), dim3(NT), 0, st, perm, n, nb, rb, x, ldx, xp);
     hip_check(hipGetLastError(), "gather launch");
 }
@@ -356,6 +367,8 @@ void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const do
 void launch_scatter_mrhs(const int32_t *perm, int64_t n, int nb, int rb, double alpha, const double *yp,
                          double *y, int64_t ldy, hipStream_t st)
 {
+    check_rb(rb);
+    if (nb < 1 || nb > rb) fail(H2B_EINVAL, "block holds 1..rb right-hand sides");
     hipLaunchKernelGGL(k_scatter_mrhs, dim3(grid_for(n * nb)), dim3(NT), 0, st, perm, n, nb, rb, alpha, yp, y,
                        ldy);
     hip_check(hipGetLastError(), "scatter launch");

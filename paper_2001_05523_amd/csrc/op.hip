@@ -413,8 +413,17 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
 
 // ------------------------------------------------ many right-hand sides
 
+// Block width for nrhs right-hand sides: the block kernels exist for 16, 32
+// and 64 columns only.
+static int block_width(const Op &op, int nrhs)
+{
+    if (op.tune_rb > 0) return op.tune_rb;
+    return nrhs <= 16 ? 16 : nrhs <= 32 ? 32 : 64;
+}
+
 static void ensure_block_buffers(Op &op, int rb)
 {
+    if (rb != 16 && rb != 32 && rb != 64) fail(H2B_EINVAL, "block width must be 16, 32 or 64");
     if (op.mrhs_rb >= rb) return;
     const int64_t nmax = std::max(op.nrows, op.ncols);
     const int64_t hmax = std::max<int64_t>(std::max(op.rowb->hat_total, op.colb->hat_total), 1);
@@ -494,7 +503,7 @@ static void product(Op &op, int trans, double alpha, const double *x, int64_t ld
         product_one<F, C>(op, trans, alpha, x, y, st);
         return;
     }
-    const int rb = op.tune_rb > 0 ? op.tune_rb : std::min(64, (nrhs + 15) / 16 * 16);
+    const int rb = block_width(op, nrhs);
     ensure_block_buffers(op, rb);
     for (int c = 0; c < nrhs; c += rb)
         product_block<F, C>(op, trans, alpha, x + c * ldx, ldx, y + c * ldy, ldy, std::min(rb, nrhs - c), rb, st);
@@ -519,7 +528,7 @@ void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, c
 
 void prepare_product(Op &op, int nrhs)
 {
-    if (nrhs > 1) ensure_block_buffers(op, op.tune_rb > 0 ? op.tune_rb : std::min(64, (nrhs + 15) / 16 * 16));
+    if (nrhs > 1) ensure_block_buffers(op, block_width(op, nrhs));
 }
 
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,

@@ -232,13 +232,15 @@ def _run_block(op, X, trans=False, alpha=1.0):
 @pytest.mark.parametrize("nrhs", [64, 37])
 def test_many_right_hand_sides(dtype, nrhs):
     """Blocks of right-hand sides (GEMM form, matrix cores for the FP32/BF16
-    coupling) agree with the single-vector products of the same operator:
-    FP64 to rounding, FP32 to 1e-5, BF16 within its 8-bit mantissa."""
+    coupling) agree with the single-vector FP64 products of the same
+    (recompressed, orthonormal-basis) operator: FP64 to rounding, FP32 to
+    1e-5, BF16 within its 8-bit mantissa."""
     h = _lib()
     v, t = synth.octa_sphere(16)
     for kernel in ("slp", "dlp"):
-        op = h.Operator(v, t, kernel=kernel, leaf=16, order_m=3, q_near=4, farfield_dtype=dtype)
-        ref_op = op if dtype == "f64" else h.Operator(v, t, kernel=kernel, leaf=16, order_m=3, q_near=4)
+        kw = dict(kernel=kernel, leaf=16, order_m=4, q_near=4, recompress_tol=1e-6)
+        op = h.Operator(v, t, farfield_dtype=dtype, **kw)
+        ref_op = op if dtype == "f64" else h.Operator(v, t, **kw)
         for trans in (False, True):
             nin = op.shape[0] if trans else op.shape[1]
             X = synth.random_vector(nin, 301, cols=nrhs)
