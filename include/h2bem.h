@@ -224,6 +224,31 @@ h2b_status h2b_batch_destroy(h2b_batch batch);
  * Errors: H2B_EINVAL for nrhs outside 2..64. */
 h2b_status h2b_op_tune(h2b_op op, int nrhs, void *hip_stream, double *best_us);
 
+/* Shape derivatives.  Both calls keep the cluster trees, block tree, boxes and
+ * Chebyshev points of the operator frozen at the geometry it was assembled
+ * for; only the near-field entries and the leaf bases depend on the vertex
+ * coordinates.  Operators with recompress_tol > 0 are not supported
+ * (H2B_ENOTSUP).
+ *
+ * h2b_op_set_geometry: new vertex coordinates (host arrays, nv each, same
+ * triangles); re-assembles the near field and the leaf bases, synchronises
+ * hip_stream.  Errors: H2B_EINVAL for non-finite coordinates or a zero-area
+ * triangle.
+ *
+ * h2b_slp_shape_grad: (gvx, gvy, gvz) += d(x^T G y)/d(vertex coordinates) for
+ * the H^2 approximation of G (Section 1, eq. (slp)): the adjoint of the
+ * near-field quadrature (every stored entry weighted by x_i y_j) plus the
+ * derivative of the leaf-basis integrals weighted by the leaf coefficients of
+ * the two partial products S V^T y and S V^T x (the far field is symmetric,
+ * S_st = S_ts^T).  x, y: device arrays of nt doubles (triangle order);
+ * gvx, gvy, gvz: device arrays of nv doubles (vertex order), accumulated
+ * with atomics.  Runs asynchronously on hip_stream.
+ * Errors: H2B_EINVAL if the operator is not G or a pointer is NULL. */
+h2b_status h2b_op_set_geometry(h2b_op op, const double *vx, const double *vy, const double *vz,
+                               void *hip_stream);
+h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double *gvx, double *gvy,
+                              double *gvz, void *hip_stream);
+
 /* Per-phase timing of the products on an operator, measured with HIP events on
  * each product's own stream.  h2b_op_set_timing(op, 1) starts recording (one
  * event set per single-vector product, created on the host as needed);

@@ -74,6 +74,8 @@ _SIGS = {
     "h2b_batch_create": ([ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_vp)], ctypes.c_int),
     "h2b_batch_launch": ([_vp, _vp], ctypes.c_int),
     "h2b_batch_destroy": ([_vp], ctypes.c_int),
+    "h2b_op_set_geometry": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_slp_shape_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
 }
@@ -237,6 +239,23 @@ class Operator:
         _check(h2b_op_tune(self.handle, int(nrhs), _stream_ptr(stream), ctypes.byref(best)))
         return best.value
 
+    def set_geometry(self, verts, stream=None):
+        """New vertex coordinates (same triangles); trees, boxes and
+        interpolation points stay frozen."""
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, 3))
+        if len(v) != self.mesh.nv:
+            raise ValueError("expected %d vertices" % self.mesh.nv)
+        vx, vy, vz = (np.ascontiguousarray(v[:, d]) for d in range(3))
+        _check(h2b_op_set_geometry(self.handle, _ptr(vx), _ptr(vy), _ptr(vz), _stream_ptr(stream)))
+
+    def shape_grad(self, x, y, stream=None):
+        """d(x^T G y)/d(vertex coordinates) as an (nv, 3) float64 CUDA tensor."""
+        import torch
+        g = torch.zeros((3, self.mesh.nv), dtype=torch.float64, device=x.device)
+        _check(h2b_slp_shape_grad(self.handle, _vp(x.data_ptr()), _vp(y.data_ptr()), _vp(g[0].data_ptr()),
+                                  _vp(g[1].data_ptr()), _vp(g[2].data_ptr()), _stream_ptr(stream)))
+        return g.t()
+
     def set_timing(self, on=True):
         _check(h2b_op_set_timing(self.handle, int(bool(on))))
 
@@ -284,3 +303,31 @@ class Batch:
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+
+
+class SlpBilinear(torch.autograd.Function):
+    """b = x^T G(verts) y for the H^2 single-layer matrix of an Operator built
+    with recompress_tol = 0; the cluster trees, boxes and interpolation points
+    stay frozen at the operator's construction geometry.  The backward pass
+    uses the library's adjoint kernels for d b / d verts and the products
+    G y and G^T x for the vectors.
+
+        b = SlpBilinear.apply(verts, x, y, op)"""
+
+    @staticmethod
+    def forward(ctx, verts, x, y, op):
+        op.set_geometry(verts.detach().cpu().numpy())
+        gy = torch.zeros_like(x)
+        op.matvec(y, gy)
+        ctx.save_for_backward(x, y, gy)
+        ctx.op = op
+        return torch.dot(x, gy)
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, y, gy = ctx.saved_tensors
+        op = ctx.op
+        gverts = op.shape_grad(x, y)
+        gtx = torch.zeros_like(y)
+        op.matvec(x, gtx, trans=True)
+        return (gout * gverts).to(torch.float64), gout * gy, gout * gtx, None

@@ -259,6 +259,24 @@ h2b_status h2b_op_tune(h2b_op op, int nrhs, void *hip_stream, double *best_us)
     });
 }
 
+h2b_status h2b_op_set_geometry(h2b_op op, const double *vx, const double *vy, const double *vz,
+                               void *hip_stream)
+{
+    return guarded([&] {
+        need(op, "op");
+        h2b::set_geometry(*op->op, vx, vy, vz, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double *gvx, double *gvy,
+                              double *gvz, void *hip_stream)
+{
+    return guarded([&] {
+        need(G, "G");
+        h2b::slp_shape_grad(*G->op, x, y, gvx, gvy, gvz, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 h2b_status h2b_op_set_timing(h2b_op op, int enable)
 {
     return guarded([&] {

@@ -53,6 +53,16 @@ template <typename T>
 void launch_coupling(const RowPanels &rp, const double *raxes, const double *caxes, int m, T *vals,
                      hipStream_t st);
 
+// Shape derivative of x^T G y: near-field entries (every stored (i, j) with
+// weight x_i y_j) and leaf bases (coefficients x_i a_t(y) + y_i a_t(x)), added
+// into the vertex gradient arrays gx, gy, gz.
+void launch_near_grad(const RowPanels &rp, const int32_t *perm, const GeoDev &geo, const QuadDev &quad,
+                      const double *xp, const double *yp, double *gx, double *gy, double *gz, hipStream_t st);
+template <typename F>
+void launch_leaf_grad(const RowPanels &leaf, const int32_t *perm, const double *axes, int m, const GeoDev &geo,
+                      const QuadDev &quad, const F *ax, const F *ay, const double *xp, const double *yp,
+                      double *gx, double *gy, double *gz, hipStream_t st);
+
 // --------------------------------------------------------------- product
 
 // Step of the product a panel launch belongs to; each gets its own kernel

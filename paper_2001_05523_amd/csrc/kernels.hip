@@ -439,6 +439,205 @@ __global__ __launch_bounds__(NT) void k_coupling(RowPanelDev d, const double *__
 }
 
 // ===================================================================
+//  Shape derivatives (frozen trees, boxes and interpolation points)
+// ===================================================================
+
+// d|e1 x e2| / d(corner c) for the parametrisation P0 + u1 e1 + u2 e2,
+// e1 = P1 - P0, e2 = P2 - P1: with n the unit normal, dJ = (e2 x n).de1 +
+// (n x e1).de2.
+__device__ inline void jac_grad(const Tri &T, double J, double out[3][3])
+{
+    double n[3] = {T.e1[1] * T.e2[2] - T.e1[2] * T.e2[1], T.e1[2] * T.e2[0] - T.e1[0] * T.e2[2],
+                   T.e1[0] * T.e2[1] - T.e1[1] * T.e2[0]};
+    for (int d = 0; d < 3; ++d) n[d] /= J;
+    const double a[3] = {T.e2[1] * n[2] - T.e2[2] * n[1], T.e2[2] * n[0] - T.e2[0] * n[2],
+                         T.e2[0] * n[1] - T.e2[1] * n[0]};  // e2 x n
+    const double b[3] = {n[1] * T.e1[2] - n[2] * T.e1[1], n[2] * T.e1[0] - n[0] * T.e1[2],
+                         n[0] * T.e1[1] - n[1] * T.e1[0]};  // n x e1
+    for (int d = 0; d < 3; ++d) {
+        out[0][d] = -a[d];
+        out[1][d] = a[d] - b[d];
+        out[2][d] = b[d];
+    }
+}
+
+// Adds w * dG_ij / d(vertex coordinates) into g (3 arrays), G_ij being the
+// regularised-quadrature value of slp_entry: derivative of the same rule with
+// respect to the corners, through the Jacobians and through x - y (the xi
+// integral of the touching rules again in closed form).
+__device__ void slp_entry_grad(const GeoDev &g, int i, int j, const QuadDev &Q, double w, double *gx,
+                               double *gy, double *gz)
+{
+    int vi[3] = {g.t0[i], g.t1[i], g.t2[i]};
+    int vj[3] = {g.t0[j], g.t1[j], g.t2[j]};
+    int oi[3], oj[3];
+    const int ns = pair_slots(vi, vj, oi, oj);
+    Tri X, Y;
+    load_tri(g, vi[oi[0]], vi[oi[1]], vi[oi[2]], X);
+    load_tri(g, vj[oj[0]], vj[oj[1]], vj[oj[2]], Y);
+    double I = 0.0, dX[3][3] = {{0}}, dY[3][3] = {{0}};
+    if (ns == 0) {
+        for (int a = 0; a < Q.q; ++a) {
+            const double u = Q.t[a];
+            for (int b = 0; b < Q.q; ++b) {
+                const double v = u * Q.t[b];
+                const double wx = Q.w[a] * Q.w[b] * u;
+                const double lx[3] = {1.0 - u, u - v, v};
+                double x[3];
+                for (int d = 0; d < 3; ++d) x[d] = X.p[d] + u * X.e1[d] + v * X.e2[d];
+                for (int c = 0; c < Q.q; ++c) {
+                    const double s = Q.t[c];
+                    for (int e = 0; e < Q.q; ++e) {
+                        const double sv = s * Q.t[e];
+                        const double wq = wx * Q.w[c] * Q.w[e] * s;
+                        const double ly[3] = {1.0 - s, s - sv, sv};
+                        double dd[3];
+                        for (int d = 0; d < 3; ++d) dd[d] = x[d] - (Y.p[d] + s * Y.e1[d] + sv * Y.e2[d]);
+                        const double ir = rsqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+                        const double ir3 = wq * ir * ir * ir;
+                        I += wq * ir;
+                        for (int k = 0; k < 3; ++k)
+                            for (int d = 0; d < 3; ++d) {
+                                dX[k][d] -= lx[k] * dd[d] * ir3;
+                                dY[k][d] += ly[k] * dd[d] * ir3;
+                            }
+                    }
+                }
+            }
+        }
+    } else {
+        const int nreg = (ns == 3) ? 6 : (ns == 2) ? 5 : 2;
+        for (int r = 0; r < nreg; ++r)
+            for (int a = 0; a < Q.q; ++a)
+                for (int b = 0; b < Q.q; ++b)
+                    for (int c = 0; c < Q.q; ++c) {
+                        double xd[2], yd[2];
+                        const double jac = ss_dirs(ns, r, Q.t[a], Q.t[b], Q.t[c], xd, yd);
+                        const double wq = Q.w[a] * Q.w[b] * Q.w[c] * jac;
+                        double D[3];
+                        for (int d = 0; d < 3; ++d)
+                            D[d] = xd[0] * X.e1[d] + xd[1] * X.e2[d] - yd[0] * Y.e1[d] - yd[1] * Y.e2[d];
+                        const double ir = rsqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+                        const double ir3 = wq * ir * ir * ir;
+                        I += wq * ir * (1.0 / 3.0);
+                        // int_0^1 xi * barycentric(xi X) d xi
+                        const double lx[3] = {0.5 - xd[0] * (1.0 / 3.0), (xd[0] - xd[1]) * (1.0 / 3.0),
+                                              xd[1] * (1.0 / 3.0)};
+                        const double ly[3] = {0.5 - yd[0] * (1.0 / 3.0), (yd[0] - yd[1]) * (1.0 / 3.0),
+                                              yd[1] * (1.0 / 3.0)};
+                        for (int k = 0; k < 3; ++k)
+                            for (int d = 0; d < 3; ++d) {
+                                dX[k][d] -= lx[k] * D[d] * ir3;
+                                dY[k][d] += ly[k] * D[d] * ir3;
+                            }
+                    }
+    }
+    const double Jx = tri_jac(X), Jy = tri_jac(Y);
+    double gJx[3][3], gJy[3][3];
+    jac_grad(X, Jx, gJx);
+    jac_grad(Y, Jy, gJy);
+    const double s = w * INV_4PI;
+    for (int k = 0; k < 3; ++k) {
+        const int vx = vi[oi[k]], vy = vj[oj[k]];
+        double ax[3], ay[3];
+        for (int d = 0; d < 3; ++d) {
+            ax[d] = s * (gJx[k][d] * Jy * I + Jx * Jy * dX[k][d]);
+            ay[d] = s * (Jx * gJy[k][d] * I + Jx * Jy * dY[k][d]);
+        }
+        atomicAdd(gx + vx, ax[0]);
+        atomicAdd(gy + vx, ax[1]);
+        atomicAdd(gz + vx, ax[2]);
+        atomicAdd(gx + vy, ay[0]);
+        atomicAdd(gy + vy, ay[1]);
+        atomicAdd(gz + vy, ay[2]);
+    }
+}
+
+// Near-field part of d(x^T G y)/dV: every stored entry (i, j) contributes
+// x_i y_j dG_ij.  xp, yp in cluster order.
+__global__ __launch_bounds__(NT) void k_near_grad(RowPanelDev d, const int32_t *__restrict__ perm, GeoDev geo,
+                                                  QuadDev Q, const double *__restrict__ xp,
+                                                  const double *__restrict__ yp, double *gx, double *gy,
+                                                  double *gz)
+{
+    const int g = blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int ob = d.out_begin[g];
+    const int64_t n = (int64_t)nr * nc;
+    for (int64_t e = threadIdx.x; e < n; e += NT) {
+        const int r = (int)(e / nc), c = (int)(e % nc);
+        const int cpos = panel_column(d, g, c);
+        const double w = xp[ob + r] * yp[cpos];
+        if (w == 0.0) continue;
+        slp_entry_grad(geo, perm[ob + r], perm[cpos], Q, w, gx, gy, gz);
+    }
+}
+
+// Far-field part through the leaf bases: for triangle i of leaf t with
+// coefficients c = x_i a_t(y) + y_i a_t(x) (a = leaf coefficients of the
+// partial products), adds d/dV of int_{tau_i} sum_nu c_nu L_{t,nu}.
+template <typename F>
+__global__ __launch_bounds__(NT) void k_leaf_grad(RowPanelDev d, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ axes, int m, GeoDev geo, QuadDev Q,
+                                                  const F *__restrict__ ax, const F *__restrict__ ay,
+                                                  const double *__restrict__ xp, const double *__restrict__ yp,
+                                                  double *gx, double *gy, double *gz)
+{
+    const int g = blockIdx.x;
+    const int cl = d.tag[g];
+    const int k = d.nrows[g], n = d.ncols[g];
+    const int in0 = d.seg_in[d.seg_ptr[g]];
+    const int hb = d.out_begin[g];
+    __shared__ double axs[3 * MMAX];
+    if (threadIdx.x < 3 * m) axs[threadIdx.x] = axes[(int64_t)cl * 3 * m + threadIdx.x];
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += NT) {
+        const int tri = perm[in0 + r];
+        const double xr = xp[in0 + r], yr = yp[in0 + r];
+        Tri T;
+        load_tri(geo, geo.t0[tri], geo.t1[tri], geo.t2[tri], T);
+        const double J = tri_jac(T);
+        double S = 0.0, Tc[3][3] = {{0}};
+        for (int a = 0; a < Q.q; ++a) {
+            const double u = Q.t[a];
+            for (int b = 0; b < Q.q; ++b) {
+                const double v = u * Q.t[b];
+                const double wq = Q.w[a] * Q.w[b] * u;
+                double p[3];
+                for (int dd = 0; dd < 3; ++dd) p[dd] = T.p[dd] + u * T.e1[dd] + v * T.e2[dd];
+                double l[3][MMAX], dl[3][MMAX];
+                for (int dd = 0; dd < 3; ++dd)
+                    for (int q = 0; q < m; ++q) {
+                        l[dd][q] = lag1(axs + dd * m, m, q, p[dd]);
+                        dl[dd][q] = lag1d(axs + dd * m, m, q, p[dd]);
+                    }
+                double f = 0.0, gf[3] = {0.0, 0.0, 0.0};
+                for (int nu = 0; nu < k; ++nu) {
+                    const double cnu = xr * (double)ay[hb + nu] + yr * (double)ax[hb + nu];
+                    const int n1 = nu % m, n2 = (nu / m) % m, n3 = nu / (m * m);
+                    f += cnu * l[0][n1] * l[1][n2] * l[2][n3];
+                    gf[0] += cnu * dl[0][n1] * l[1][n2] * l[2][n3];
+                    gf[1] += cnu * l[0][n1] * dl[1][n2] * l[2][n3];
+                    gf[2] += cnu * l[0][n1] * l[1][n2] * dl[2][n3];
+                }
+                S += wq * f;
+                const double lam[3] = {1.0 - u, u - v, v};
+                for (int c = 0; c < 3; ++c)
+                    for (int dd = 0; dd < 3; ++dd) Tc[c][dd] += wq * lam[c] * gf[dd];
+            }
+        }
+        double gJ[3][3];
+        jac_grad(T, J, gJ);
+        const int vv[3] = {geo.t0[tri], geo.t1[tri], geo.t2[tri]};
+        for (int c = 0; c < 3; ++c) {
+            atomicAdd(gx + vv[c], gJ[c][0] * S + J * Tc[c][0]);
+            atomicAdd(gy + vv[c], gJ[c][1] * S + J * Tc[c][1]);
+            atomicAdd(gz + vv[c], gJ[c][2] * S + J * Tc[c][2]);
+        }
+    }
+}
+
+// ===================================================================
 //  Panel products
 // ===================================================================
 
@@ -644,6 +843,26 @@ void launch_near_assemble(h2b_kernel kernel, const RowPanels &rp, const int32_t 
         hipLaunchKernelGGL(k_near_assemble<1>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, rperm,
                            cperm, geo, quad, vals);
     hip_check(hipGetLastError(), "nearfield assembly launch");
+}
+
+void launch_near_grad(const RowPanels &rp, const int32_t *perm, const GeoDev &geo, const QuadDev &quad,
+                      const double *xp, const double *yp, double *gx, double *gy, double *gz, hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_near_grad, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, perm, geo, quad, xp, yp, gx, gy,
+                       gz);
+    hip_check(hipGetLastError(), "nearfield gradient launch");
+}
+
+template <typename F>
+void launch_leaf_grad(const RowPanels &leaf, const int32_t *perm, const double *axes, int m, const GeoDev &geo,
+                      const QuadDev &quad, const F *ax, const F *ay, const double *xp, const double *yp,
+                      double *gx, double *gy, double *gz, hipStream_t st)
+{
+    if (leaf.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_leaf_grad<F>, dim3(leaf.ngroups()), dim3(NT), 0, st, leaf.dev, perm, axes, m, geo, quad,
+                       ax, ay, xp, yp, gx, gy, gz);
+    hip_check(hipGetLastError(), "leaf gradient launch");
 }
 
 template <typename T>
@@ -888,6 +1107,12 @@ template void launch_coupling<float>(const RowPanels &, const double *, const do
 template void launch_coupling<bf16_t>(const RowPanels &, const double *, const double *, int, bf16_t *,
                                       hipStream_t);
 template void launch_fill_zero<double>(double *, int64_t, hipStream_t);
+template void launch_leaf_grad<double>(const RowPanels &, const int32_t *, const double *, int, const GeoDev &,
+                                       const QuadDev &, const double *, const double *, const double *,
+                                       const double *, double *, double *, double *, hipStream_t);
+template void launch_leaf_grad<float>(const RowPanels &, const int32_t *, const double *, int, const GeoDev &,
+                                      const QuadDev &, const float *, const float *, const double *,
+                                      const double *, double *, double *, double *, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
 template void launch_transpose_panels<double>(const RowPanels &, const double *, double *, hipStream_t);
 template void launch_transpose_panels<float>(const RowPanels &, const float *, float *, hipStream_t);

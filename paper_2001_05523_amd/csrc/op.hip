@@ -642,3 +642,111 @@ void op_stats(const Op &op, h2b_op_stats &s)
 }
 
 }  // namespace h2b
+
+namespace h2b {
+
+// ------------------------------------------------------ shape derivatives
+
+void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, hipStream_t st)
+{
+    if (!vx || !vy || !vz) fail(H2B_EINVAL, "vertex arrays must not be NULL");
+    if (op.params.recompress_tol > 0.0)
+        fail(H2B_ENOTSUP, "geometry updates keep the interpolation bases frozen; recompressed operators "
+                          "are not supported");
+    const Mesh &M = *op.rowb->tree->mesh;
+    const int64_t nv = M.nv, nt = M.nt;
+    std::vector<double> nx(nt), ny(nt), nz(nt);
+    for (int64_t v = 0; v < nv; ++v)
+        if (!std::isfinite(vx[v]) || !std::isfinite(vy[v]) || !std::isfinite(vz[v]))
+            fail(H2B_EINVAL, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < nt; ++i) {
+        const int a = M.t0[i], b = M.t1[i], c = M.t2[i];
+        const double e1[3] = {vx[b] - vx[a], vy[b] - vy[a], vz[b] - vz[a]};
+        const double e2[3] = {vx[c] - vx[a], vy[c] - vy[a], vz[c] - vz[a]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(len > 0.0)) fail(H2B_EINVAL, "triangle " + std::to_string(i) + " has zero area");
+        nx[i] = cr[0] / len;
+        ny[i] = cr[1] / len;
+        nz[i] = cr[2] / len;
+    }
+    auto up = [&](const double *src, const double *dst, int64_t n) {
+        hip_check(hipMemcpyAsync(const_cast<double *>(dst), src, sizeof(double) * n, hipMemcpyHostToDevice, st),
+                  "geometry upload");
+    };
+    up(vx, op.geo.vx, nv);
+    up(vy, op.geo.vy, nv);
+    up(vz, op.geo.vz, nv);
+    up(nx.data(), op.geo.nx, nt);
+    up(ny.data(), op.geo.ny, nt);
+    up(nz.data(), op.geo.nz, nt);
+    hip_check(hipStreamSynchronize(st), "geometry upload");
+    QuadDev Qn = make_quad(op.params.q_near);
+    launch_near_assemble(op.kernel, op.near, op.rowb->perm_dev, op.colb->perm_dev, op.geo, Qn,
+                         op.near_vals.as<double>(), st);
+    std::vector<Basis *> bases{op.rowb.get()};
+    if (op.colb != op.rowb) bases.push_back(op.colb.get());
+    const int m = op.params.order_m;
+    for (Basis *B : bases) {
+        if (op.params.farfield_dtype == H2B_F64)
+            assemble_basis<double>(*B, m, B->axes, op.geo, st);
+        else
+            assemble_basis<float>(*B, m, B->axes, op.geo, st);
+        transpose_basis_values(*B, op.params.farfield_dtype, st);
+    }
+    hip_check(hipStreamSynchronize(st), "geometry assembly");
+}
+
+// Leaf coefficients a(v) = backward transfers of S V^T v (the product
+// stopped before the leaf bases), v already in cluster order.
+template <typename F, typename C>
+static void partial_product(Op &op, const double *vp, F *a, hipStream_t st)
+{
+    const Basis &B = *op.rowb;
+    F *xhat = op.xhat.as<F>();
+    forward<F>(B, vp, xhat, st);
+    launch_fill_zero<F>(a, B.hat_total, st);
+    launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, a, true, st, Role::Coupling);
+    for (auto &s : B.bw_steps)
+        launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), a, a, st, Role::Transfer);
+}
+
+template <typename F, typename C>
+static void shape_grad_impl(Op &op, const double *x, const double *y, double *gx, double *gy, double *gz,
+                            hipStream_t st)
+{
+    const Basis &B = *op.rowb;
+    const int64_t n = op.nrows;
+    if (op.gxp.bytes < sizeof(double) * n) {
+        op.gxp.alloc(sizeof(double) * n);
+        op.gyp.alloc(sizeof(double) * n);
+        op.gax.alloc(sizeof(F) * std::max<int64_t>(B.hat_total, 1));
+        op.gay.alloc(sizeof(F) * std::max<int64_t>(B.hat_total, 1));
+    }
+    double *xp = op.gxp.as<double>(), *yp = op.gyp.as<double>();
+    launch_gather(B.perm_dev, n, 1, x, n, xp, st);
+    launch_gather(B.perm_dev, n, 1, y, n, yp, st);
+    partial_product<F, C>(op, yp, op.gay.as<F>(), st);
+    partial_product<F, C>(op, xp, op.gax.as<F>(), st);
+    launch_near_grad(op.near, B.perm_dev, op.geo, make_quad(op.params.q_near), xp, yp, gx, gy, gz, st);
+    launch_leaf_grad<F>(B.leaf, B.perm_dev, B.axes.as<double>(), op.params.order_m, op.geo,
+                        make_quad(basis_quad_order(op.params.order_m)), op.gax.as<F>(), op.gay.as<F>(), xp, yp,
+                        gx, gy, gz, st);
+}
+
+void slp_shape_grad(Op &op, const double *x, const double *y, double *gx, double *gy, double *gz,
+                    hipStream_t st)
+{
+    if (op.kernel != H2B_SLP) fail(H2B_EINVAL, "the shape gradient is implemented for the single-layer matrix");
+    if (op.params.recompress_tol > 0.0)
+        fail(H2B_ENOTSUP, "the shape gradient needs the interpolation bases (recompress_tol = 0)");
+    if (!x || !y || !gx || !gy || !gz) fail(H2B_EINVAL, "NULL vector");
+    switch (op.params.farfield_dtype) {
+    case H2B_F64: shape_grad_impl<double, double>(op, x, y, gx, gy, gz, st); break;
+    case H2B_F32: shape_grad_impl<float, float>(op, x, y, gx, gy, gz, st); break;
+    default: shape_grad_impl<float, bf16_t>(op, x, y, gx, gy, gz, st); break;
+    }
+}
+
+}  // namespace h2b

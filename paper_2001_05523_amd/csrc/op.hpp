@@ -52,6 +52,7 @@ struct Op {
     DevMem cpl_vals;
     DevMem xp, yp, xhat, yhat;              // product work vectors
     DevMem xpb, ypb, xhatb, yhatb;          // block work vectors (many right-hand sides)
+    DevMem gxp, gyp, gax, gay;              // shape-gradient work vectors
     int mrhs_rb = 0;                        // block width the block vectors are sized for
     int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)
     bool timing = false;
@@ -94,6 +95,12 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
 void batch_launch(Batch &b, hipStream_t st);
 void phase_times(Op &op, double out[6]);
 void tune(Op &op, int nrhs, hipStream_t st, double *best_us);
+// Re-assembles the geometry-dependent parts (near field, leaf bases) for new
+// vertex coordinates with trees, boxes and interpolation points frozen.
+void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, hipStream_t st);
+// (gx, gy, gz) += d(x^T G y)/d(vertex coordinates) for the frozen structure.
+void slp_shape_grad(Op &op, const double *x, const double *y, double *gx, double *gy, double *gz,
+                    hipStream_t st);
 void op_stats(const Op &op, h2b_op_stats &s);
 
 }  // namespace h2b
