@@ -321,6 +321,7 @@ class SlpBilinear(torch.autograd.Function):
         op.matvec(y, gy)
         ctx.save_for_backward(x, y, gy)
         ctx.op = op
+        ctx.vspec = (verts.device, verts.dtype)
         return torch.dot(x, gy)
 
     @staticmethod
@@ -330,4 +331,5 @@ class SlpBilinear(torch.autograd.Function):
         gverts = op.shape_grad(x, y)
         gtx = torch.zeros_like(y)
         op.matvec(x, gtx, trans=True)
-        return (gout * gverts).to(torch.float64), gout * gy, gout * gtx, None
+        gv = (gout * gverts).to(device=ctx.vspec[0], dtype=ctx.vspec[1])
+        return gv, gout * gy, gout * gtx, None
