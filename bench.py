@@ -8,9 +8,10 @@ i.e. 2,097,152 triangles and 1,048,578 vertices; leaf size 64, eta = 1,
 Chebyshev order 4, near-field quadrature order 6 (Table 1 for this n).
 x ~ N(0,1) from seeds 501 (G) and 502 (K).
 
-A step is one G x and one K x (all phases of the H^2 product: gather, forward
-transformation, coupling, backward transformation, near field, scatter) with
-the operators and vectors resident in HBM.  The plain FP64 method is the timed
+A step is G x, G^T x, K x and K^T x (every phase of the H^2 product: gather,
+forward transformation, coupling, backward transformation, near field,
+scatter; the near field runs on its own stream beside the far field) with the
+operators and vectors resident in HBM.  The plain FP64 method is the timed
 value; the mixed form (FP32 bases and coupling matrices, FP32 accumulation,
 FP64 near field) is timed beside it and its deviation from FP64 reported.
 
@@ -58,29 +59,40 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def alg_bytes(info, fsz):
-    """Algorithmic bytes of one single-vector product, and of its coupling and
-    nearfield launches: every stored entry read once, every vector entry read
-    once and written once (y read-modify-write counted twice)."""
-    vec = 8 * (info["rows"] + 2 * info["rows"] + info["cols"])  # gather/scatter/x/y
-    near = 8 * info["near_entries"] + 8 * (info["cols"] + 2 * info["rows"])
-    cpl = fsz * info["coupling_entries"] + fsz * (info["col_coeffs"] + 2 * info["row_coeffs"])
+def alg_bytes(info, fsz, trans=False):
+    """Algorithmic bytes of one single-vector product A x (or A^T x), and of its
+    coupling and nearfield launches: every stored entry read once, every
+    vector entry read once and written once (y read-modify-write counted
+    twice)."""
+    nin, nout = (info["rows"], info["cols"]) if trans else (info["cols"], info["rows"])
+    hin, hout = (info["row_coeffs"], info["col_coeffs"]) if trans else (info["col_coeffs"], info["row_coeffs"])
+    vec = 8 * (nout + 2 * nout + nin)  # gather/scatter/x/y
+    near = 8 * info["near_entries"] + 8 * (nin + 2 * nout)
+    cpl = fsz * info["coupling_entries"] + fsz * (hin + 2 * hout)
     bases = fsz * (info["row_basis_entries"] + info["col_basis_entries"])
     total = near + cpl + bases + vec
     return dict(total=total, near=near, coupling=cpl, bases=bases)
 
 
-def time_steps(torch, ops, xs, ys, steps, warmup):
+def time_steps(torch, items, steps, warmup):
+    """Times `steps` passes over items = [(op, x, y, trans), ...] after `warmup`
+    untimed passes, with the operators' phase events recorded on the streams
+    the phases run on.  Returns ms per pass and each operator's mean phase
+    times (over its products in the pass)."""
+    ops = []
+    for it in items:
+        if all(it[0] is not o for o in ops):
+            ops.append(it[0])
     for _ in range(warmup):
-        for op, x, y in zip(ops, xs, ys):
-            op.matvec(x, y)
+        for op, x, y, tr in items:
+            op.matvec(x, y, trans=tr)
     torch.cuda.synchronize()
     for op in ops:
         op.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        for op, x, y in zip(ops, xs, ys):
-            op.matvec(x, y)
+        for op, x, y, tr in items:
+            op.matvec(x, y, trans=tr)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phases = [op.phase_times() for op in ops]
@@ -89,16 +101,30 @@ def time_steps(torch, ops, xs, ys, steps, warmup):
     return (t1 - t0) * 1e3 / steps, phases
 
 
-def cpu_baseline(verts, tris, q, rows_g, rows_k, x_g, x_k):
+def time_product(torch, op, x, y, trans, reps=10):
+    """ms per product of one operator and direction alone (no events)."""
+    op.matvec(x, y, trans=trans)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        op.matvec(x, y, trans=trans)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def cpu_baseline(verts, tris, q, sample, xin):
+    """Oracle rows of G and K on the host's cores."""
     import oracle
     oracle.build(force=False)
     threads = oracle.get_threads()
-    t0 = time.perf_counter()
-    yg = oracle.slp_rows(verts, tris, q, rows_g, x_g)
-    t1 = time.perf_counter()
-    yk = oracle.dlp_rows(verts, tris, q, rows_k, x_k)
-    t2 = time.perf_counter()
-    return dict(yg=yg, yk=yk, tg=t1 - t0, tk=t2 - t1, threads=threads)
+    fn = {"G": (oracle.slp_rows, False), "K": (oracle.dlp_rows, False)}
+    y, t = {}, {}
+    for p, rows in sample.items():
+        f, tr = fn[p]
+        t0 = time.perf_counter()
+        y[p] = f(verts, tris, q, rows, xin[p], trans=tr)
+        t[p] = time.perf_counter() - t0
+    return dict(y=y, t=t, threads=threads)
 
 
 def main():
@@ -153,55 +179,76 @@ def main():
                                        inf["bytes_far"] / 1e9, inf["nfar"], inf["nnear"],
                                        inf["mean_rank_row"], inf["mean_rank_col"]))
 
-    Xg = torch.tensor(x_g, device=dev)
-    Xk = torch.tensor(x_k, device=dev)
-    Yg = torch.zeros(nt, dtype=torch.float64, device=dev)
-    Yk = torch.zeros(nt, dtype=torch.float64, device=dev)
+    # inputs of the four products: G x, G^T x (x on triangles), K x (x on
+    # vertices), K^T x (x on triangles)
+    x_gt = synth.random_vector(nt, 511)
+    x_kt = synth.random_vector(nt, 512)
+    X = {"G": torch.tensor(x_g, device=dev), "GT": torch.tensor(x_gt, device=dev),
+         "K": torch.tensor(x_k, device=dev), "KT": torch.tensor(x_kt, device=dev)}
+    Y = {"G": torch.zeros(nt, dtype=torch.float64, device=dev),
+         "GT": torch.zeros(nt, dtype=torch.float64, device=dev),
+         "K": torch.zeros(nt, dtype=torch.float64, device=dev),
+         "KT": torch.zeros(nv, dtype=torch.float64, device=dev)}
+    PRODUCTS = (("G", "G", False), ("GT", "G", True), ("K", "K", False), ("KT", "K", True))
+
+    def step_items(suffix):
+        return [(ops[o + suffix], X[p], Y[p], tr) for p, o, tr in PRODUCTS]
 
     # one clean product of each for accuracy
-    def single(op, X):
-        Y = torch.zeros(nt, dtype=torch.float64, device=dev)
-        op.matvec(X, Y)
+    def single(op, p, tr):
+        out = torch.zeros_like(Y[p])
+        op.matvec(X[p], out, trans=tr)
         torch.cuda.synchronize()
-        return Y.cpu().numpy()
+        return out.cpu().numpy()
 
-    y = {name: single(ops[name], Xg if name.startswith("G") else Xk) for name in ops}
+    y = {}
+    for suffix in ("", "32") if not args.no_mixed else ("",):
+        for p, o, tr in PRODUCTS:
+            y[p + suffix] = single(ops[o + suffix], p, tr)
 
-    ms64, ph64 = time_steps(torch, [ops["G"], ops["K"]], [Xg, Xk], [Yg, Yk], args.steps, args.warmup)
-    log("FP64 step (G x + K x): %.3f ms" % ms64)
-    res = {}
+    ms64, ph64 = time_steps(torch, step_items(""), args.steps, args.warmup)
+    log("FP64 step (G x, G^T x, K x, K^T x): %.3f ms" % ms64)
     if not args.no_mixed:
-        ms32, ph32 = time_steps(torch, [ops["G32"], ops["K32"]], [Xg, Xk], [Yg, Yk], args.steps,
-                                args.warmup)
+        ms32, ph32 = time_steps(torch, step_items("32"), args.steps, args.warmup)
         log("mixed step: %.3f ms" % ms32)
 
-    # per-operator detail
+    # per-operator detail: phases (mean over the operator's A x and A^T x in
+    # the timed steps) and each product timed alone
     detail = {}
     dominant = None
+    step_bytes = {"": 0, "32": 0}
     for name, ph in (("G", ph64[0]), ("K", ph64[1])) + ((("G32", ph32[0]), ("K32", ph32[1]))
                                                          if not args.no_mixed else ()):
         inf = ops[name].info()
         fsz = 4 if name.endswith("32") else 8
-        b = alg_bytes(inf, fsz)
-        ms = sum(ph.values())
-        d = dict(ms=ms, phases_ms=ph, alg_bytes=b["total"], gbps=b["total"] / ms / 1e6,
+        b, bt = alg_bytes(inf, fsz), alg_bytes(inf, fsz, trans=True)
+        suffix = "32" if name.endswith("32") else ""
+        base = name[0]
+        t_a = time_product(torch, ops[name], X[base], Y[base], False)
+        t_t = time_product(torch, ops[name], X[base + "T"], Y[base + "T"], True)
+        step_bytes[suffix] += b["total"] + bt["total"]
+        d = dict(ms_Ax=t_a, ms_ATx=t_t, gbps_Ax=b["total"] / t_a / 1e6, gbps_ATx=bt["total"] / t_t / 1e6,
+                 phases_ms=ph, alg_bytes_Ax=b["total"], alg_bytes_ATx=bt["total"],
                  coupling_gbps=b["coupling"] / ph["coupling"] / 1e6,
                  near_gbps=b["near"] / ph["nearfield"] / 1e6,
                  bytes_near=inf["bytes_near"], bytes_far=inf["bytes_far"],
+                 bytes_transposed=inf["bytes_transposed"],
                  nfar=inf["nfar"], nnear=inf["nnear"], assembly_s=assembly_s[name],
                  mean_rank=(inf["mean_rank_row"], inf["mean_rank_col"]),
                  max_rank=(inf["max_rank_row"], inf["max_rank_col"]))
         detail[name] = d
-        if not name.endswith("32"):
+        log("%s: A x %.3f ms (%.0f GB/s), A^T x %.3f ms (%.0f GB/s)" % (name, t_a, d["gbps_Ax"], t_t,
+                                                                        d["gbps_ATx"]))
+        if not suffix:
             for kname, ms_k, by in (("coupling", ph["coupling"], b["coupling"]),
                                     ("nearfield", ph["nearfield"], b["near"])):
                 if dominant is None or ms_k > dominant[2]:
                     dominant = (name, kname, ms_k, by)
-    for base in ("G", "K"):
-        if not args.no_mixed:
-            a, r = y[base + "32"], y[base]
-            detail[base + "32"]["rel_diff_vs_fp64"] = float(np.linalg.norm(a - r) / np.linalg.norm(r))
-    step_bytes = detail["G"]["alg_bytes"] + detail["K"]["alg_bytes"]
+    if not args.no_mixed:
+        for p, o, tr in PRODUCTS:
+            a, r = y[p + "32"], y[p]
+            detail[o + "32"]["rel_diff_vs_fp64" + ("_T" if tr else "")] = float(
+                np.linalg.norm(a - r) / np.linalg.norm(r))
     traffic_config = {"s": args.s, "leaf": args.leaf, "order": args.order, "q_near": args.q_near,
                       "tol": args.tol}
 
@@ -219,16 +266,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "unit sphere (octahedron split s=%d, %d triangles, %d vertices): one G x "
-                        "and one K x per step, H^2 Chebyshev order %d recompressed to %g, leaf %d, "
+            "workload": "unit sphere (octahedron split s=%d, %d triangles, %d vertices): G x, G^T x, "
+                        "K x and K^T x per step, H^2 Chebyshev order %d recompressed to %g, leaf %d, "
                         "eta 1, q_near %d" % (args.s, nt, nv, args.order, args.tol, args.leaf, args.q_near),
             "triangles": nt, "vertices": nv, "order_m": args.order, "leaf": args.leaf,
-            "q_near": args.q_near, "recompress_tol": args.tol, "x_seeds": [501, 502],
+            "q_near": args.q_near, "recompress_tol": args.tol, "x_seeds": [501, 511, 502, 512],
         },
-        "step_gbps": round(step_bytes / ms64 / 1e6, 1),
+        "step_gbps": round(step_bytes[""] / ms64 / 1e6, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "%s %s panel product (k_rowpanel<double, double, double, %d, *>)"
+            "kernel": "%s %s panel product, A x and A^T x launches (k_rowpanel<double, double, double, %d, *>)"
                       % (dominant[0], dominant[1], 2 if dominant[1] == "coupling" else 3),
             "achieved": round(dominant[3] / dominant[2] / 1e6, 1),
             "peak": HBM_PEAK_GBS,
@@ -242,10 +289,9 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = {"ms_per_step": round(ms32, 4), "speedup_vs_fp64": round(ms64 / ms32, 3),
-                        "rel_diff_G": detail["G32"]["rel_diff_vs_fp64"],
-                        "rel_diff_K": detail["K32"]["rel_diff_vs_fp64"],
-                        "step_gbps": round((detail["G32"]["alg_bytes"] + detail["K32"]["alg_bytes"])
-                                           / ms32 / 1e6, 1)}
+                        "rel_diff": {p: detail[o + "32"]["rel_diff_vs_fp64" + ("_T" if tr else "")]
+                                     for p, o, tr in PRODUCTS},
+                        "step_gbps": round(step_bytes["32"] / ms32 / 1e6, 1)}
 
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
@@ -262,24 +308,28 @@ def main():
         nthreads = oracle.get_threads()
         nrows = args.cpu_rows or nthreads
         rng = np.random.default_rng(503)
-        rows_g = np.sort(rng.choice(nt, nrows, replace=False))
-        rows_k = np.sort(rng.choice(nt, nrows, replace=False))
-        log("oracle: %d G rows and %d K rows on %d threads" % (nrows, nrows, nthreads))
-        cb = cpu_baseline(verts, tris, args.q_near, rows_g, rows_k, x_g, x_k)
-        est_ms = (cb["tg"] / nrows + cb["tk"] / nrows) * nt * 1e3
-        log("oracle rows: G %.1f s, K %.1f s" % (cb["tg"], cb["tk"]))
+        sample = {"G": np.sort(rng.choice(nt, nrows, replace=False)),
+                  "K": np.sort(rng.choice(nt, nrows, replace=False))}
+        xin = {"G": x_g, "K": x_k}
+        log("oracle: %d rows of each of G and K on %d threads" % (nrows, nthreads))
+        cb = cpu_baseline(verts, tris, args.q_near, sample, xin)
+        # G^T x and K^T x evaluate the same pair integrals as G x and K x; they
+        # are counted at the sampled cost of G x and K x (for K^T x a lower
+        # bound: the oracle's vertex rows evaluate each pair once per vertex)
+        est_ms = 2 * sum(cb["t"][p] / nrows * nt for p in sample) * 1e3
+        log("oracle rows: " + ", ".join("%s %.1f s" % (p, cb["t"][p]) for p in sample))
         out["cpu_baseline"] = {
             "value": est_ms, "unit": "ms", "cores": cb["threads"], "kind": "oracle",
-            "sample": "%d rows of G and %d rows of K (seed 503) of the same 2M-triangle operators, "
-                      "dense FP64 quadrature, timed %.1f s + %.1f s and scaled by n/rows to one "
-                      "dense G x + K x" % (nrows, nrows, cb["tg"], cb["tk"]),
+            "sample": "%d rows each of G and K (seed 503) of the same 2M-triangle operators, dense FP64 "
+                      "quadrature, timed %.1f s + %.1f s and scaled by n/rows to one dense G x + K x; "
+                      "G^T x and K^T x counted at the same cost (same pair integrals)"
+                      % (nrows, cb["t"]["G"], cb["t"]["K"]),
         }
         acc = {}
-        for name in ops:
-            ref = cb["yg"] if name.startswith("G") else cb["yk"]
-            rows = rows_g if name.startswith("G") else rows_k
-            got = y[name][rows]
-            acc[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        for suffix in ("", "32") if not args.no_mixed else ("",):
+            for p in sample:
+                got = y[p + suffix][sample[p]]
+                acc[p + suffix] = float(np.linalg.norm(got - cb["y"][p]) / np.linalg.norm(cb["y"][p]))
         out["sampled_row_rel_err"] = acc
     print(json.dumps(out), flush=True)
 

@@ -141,9 +141,13 @@ typedef struct {
     double recompress_tol;  /* > 0: algebraic recompression of the cluster bases to this
                                relative tolerance; 0: plain interpolation */
     h2b_dtype farfield_dtype; /* storage/arithmetic of bases and coupling matrices */
+    int transposed_copy;    /* 1: also store the nearfield and coupling matrices transposed and
+                               grouped by column cluster, so that A^T x streams rows like A x
+                               (twice that storage); 0: A^T x reads the one copy by columns */
 } h2b_params;
 
-/* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64. */
+/* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64,
+ * transposed_copy 1. */
 void h2b_params_default(h2b_params *p);
 
 /* Assembles G (kernel H2B_SLP, cols tree P0) or K (H2B_DLP, cols tree P1) on
@@ -173,6 +177,7 @@ typedef struct {
     int64_t row_coeffs, col_coeffs; /* cluster coefficients (sum of ranks), row / column tree */
     int32_t max_rank_row, max_rank_col;
     double mean_rank_row, mean_rank_col;
+    int64_t bytes_transposed;      /* device bytes of the transposed copies (0 if none) */
 } h2b_op_stats;
 
 h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
@@ -191,7 +196,13 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
  * stored matrix once per block; the coupling product of the F32/BF16 far field
  * runs on matrix cores (MFMA) with FP32 accumulation.  The first call with
  * nrhs > 1 allocates the block work vectors unless h2b_op_tune did.
- * Runs asynchronously on hip_stream.  x and y must not overlap.
+ * Runs asynchronously on hip_stream: the nearfield runs on a stream of the
+ * operator's own that is forked from hip_stream after x is read into the
+ * operator's work vector and joined back before y is written, so the call is
+ * ordered on hip_stream like a single kernel.  While hip_stream is being
+ * captured into a graph, the whole product stays on hip_stream.  The work vectors belong to the
+ * operator: products on one operator must not overlap (same stream, or ordered
+ * by the caller).  x and y must not overlap.
  * Errors: H2B_EINVAL (NULL pointers, nrhs < 1 or > 64, ld too small), H2B_EDEVICE. */
 h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
@@ -250,15 +261,19 @@ h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double
                               double *gvz, void *hip_stream);
 
 /* Per-phase timing of the products on an operator, measured with HIP events on
- * each product's own stream.  h2b_op_set_timing(op, 1) starts recording (one
- * event set per single-vector product, created on the host as needed);
- * h2b_op_phase_times waits for the last recorded product and returns the mean
- * milliseconds per product of phases[0..5] = gather, forward transformation,
- * coupling, backward transformation, nearfield, scatter, then restarts the
+ * the streams the phases run on.  A product runs its nearfield on a stream of
+ * the operator's own, forked from hip_stream after the gather and joined
+ * before the scatter, so that it overlaps the far field (forward
+ * transformation, coupling, backward transformation) on hip_stream.
+ * h2b_op_set_timing(op, 1) starts recording (one event set per product,
+ * created on the host as needed); h2b_op_phase_times waits for the last
+ * recorded product and returns the mean milliseconds per product of
+ * phases[0..6] = gather, forward transformation, coupling, backward
+ * transformation, nearfield, scatter, whole product, then restarts the
  * average.  The coupling and nearfield phases each contain exactly one kernel
  * launch.  Errors: H2B_ESTATE if nothing was recorded. */
 h2b_status h2b_op_set_timing(h2b_op op, int enable);
-h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[6]);
+h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7]);
 
 #ifdef __cplusplus
 }

@@ -180,6 +180,7 @@ void h2b_params_default(h2b_params *p)
     p->q_near = 4;
     p->recompress_tol = 0.0;
     p->farfield_dtype = H2B_F64;
+    p->transposed_copy = 1;
 }
 
 h2b_status h2b_assemble(h2b_blocks blocks, h2b_kernel kernel, const h2b_params *params,
@@ -286,7 +287,7 @@ h2b_status h2b_op_set_timing(h2b_op op, int enable)
     });
 }
 
-h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[6])
+h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7])
 {
     return guarded([&] {
         need(op, "op");

@@ -98,15 +98,20 @@ void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT 
                           bool accumulate, hipStream_t st, Role role);
 void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const double *x, int64_t ldx,
                         double *xp, hipStream_t st);
+// y[perm[k] + r*ldy] += alpha * (yp[k*rb + r] + yp2[k*rb + r]), r < nb; yp2 may be NULL
 void launch_scatter_mrhs(const int32_t *perm, int64_t n, int nb, int rb, double alpha, const double *yp,
-                         double *y, int64_t ldy, hipStream_t st);
+                         const double *yp2, double *y, int64_t ldy, hipStream_t st);
 
 // xp[k + c*n] = x[perm[k] + c*ldx]
 void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, int64_t ldx,
                    double *xp, hipStream_t st);
-// y[perm[k] + c*ldy] += alpha * yp[k + c*n]
+// y[perm[k] + c*ldy] += alpha * (yp[k + c*n] + yp2[k + c*n]); yp2 may be NULL
 void launch_scatter_add(const int32_t *perm, int64_t n, int nrhs, double alpha, const double *yp,
-                        double *y, int64_t ldy, hipStream_t st);
+                        const double *yp2, double *y, int64_t ldy, hipStream_t st);
+// Transposed copy of the values `in` of the row panels that cp describes, as
+// the row panels `out` built by regroup_transposed(cp, out).
+template <typename T>
+void launch_regroup_transpose(const ColPanels &cp, const RowPanels &out, const T *in, T *o, hipStream_t st);
 template <typename T> void launch_fill_zero(T *p, int64_t n, hipStream_t st);
 
 }  // namespace h2b

@@ -808,13 +808,15 @@ __global__ void k_gather(const int32_t *__restrict__ perm, int64_t n, int nrhs,
 }
 
 __global__ void k_scatter_add(const int32_t *__restrict__ perm, int64_t n, int nrhs, double alpha,
-                              const double *__restrict__ yp, double *__restrict__ y, int64_t ldy)
+                              const double *__restrict__ yp, const double *__restrict__ yp2,
+                              double *__restrict__ y, int64_t ldy)
 {
     const int64_t tot = n * nrhs;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / n, k = e % n;
-        y[perm[k] + c * ldy] += alpha * yp[e];
+        const double v = yp2 ? yp[e] + yp2[e] : yp[e];
+        y[perm[k] + c * ldy] += alpha * v;
     }
 }
 
@@ -1039,6 +1041,28 @@ __global__ __launch_bounds__(256) void k_transpose_panels(RowPanelDev d, const T
     }
 }
 
+// Transposed copy grouped by column: out group g collects the blocks of
+// column panel group g; entry (i, j) of block b (row i of its row panel,
+// column j of the segment) goes to row j, column c0(b) + i of group g.
+template <typename T>
+__global__ __launch_bounds__(256) void k_regroup_transpose(ColPanelDev cp, RowPanelDev out,
+                                                           const T *__restrict__ in, T *__restrict__ o)
+{
+    const int g = blockIdx.x;
+    const int nr = out.nrows[g], nc = out.ncols[g];
+    const int64_t ooff = out.val_off[g];
+    int c0 = 0;
+    for (int b = cp.blk_ptr[g]; b < cp.blk_ptr[g + 1]; ++b) {
+        const int nb = cp.b_nrows[b], stride = cp.b_stride[b];
+        const int64_t ioff = cp.b_val_off[b] + cp.b_c0[b];
+        for (int e = threadIdx.x; e < nb * nr; e += 256) {
+            const int i = e / nr, j = e % nr;
+            o[ooff + (int64_t)j * nc + c0 + i] = in[ioff + (int64_t)i * stride + j];
+        }
+        c0 += nb;
+    }
+}
+
 template <typename VT, typename XT, typename YT>
 void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const XT *x, YT *y,
                      hipStream_t st, Role role, bool accumulate)
@@ -1064,6 +1088,15 @@ void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const 
     hip_check(hipGetLastError(), "column panel launch");
 }
 
+template <typename T>
+void launch_regroup_transpose(const ColPanels &cp, const RowPanels &out, const T *in, T *o, hipStream_t st)
+{
+    if (cp.ngroups() != out.ngroups()) fail(H2B_EINVAL, "transposed copy does not match its column panels");
+    if (out.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_regroup_transpose<T>, dim3(out.ngroups()), dim3(256), 0, st, cp.dev, out.dev, in, o);
+    hip_check(hipGetLastError(), "transposed copy launch");
+}
+
 template <typename T> void launch_transpose_panels(const RowPanels &rp, const T *in, T *out, hipStream_t st)
 {
     if (rp.ngroups() == 0) return;
@@ -1079,10 +1112,10 @@ void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, in
 }
 
 void launch_scatter_add(const int32_t *perm, int64_t n, int nrhs, double alpha, const double *yp,
-                        double *y, int64_t ldy, hipStream_t st)
+                        const double *yp2, double *y, int64_t ldy, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scatter_add, dim3(blocks_for(n * nrhs)), dim3(NT), 0, st, perm, n, nrhs, alpha,
-                       yp, y, ldy);
+                       yp, yp2, y, ldy);
     hip_check(hipGetLastError(), "scatter launch");
 }
 
@@ -1115,6 +1148,12 @@ template void launch_leaf_grad<float>(const RowPanels &, const int32_t *, const 
                                       const double *, double *, double *, double *, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
 template void launch_transpose_panels<double>(const RowPanels &, const double *, double *, hipStream_t);
+template void launch_regroup_transpose<double>(const ColPanels &, const RowPanels &, const double *, double *,
+                                               hipStream_t);
+template void launch_regroup_transpose<float>(const ColPanels &, const RowPanels &, const float *, float *,
+                                              hipStream_t);
+template void launch_regroup_transpose<bf16_t>(const ColPanels &, const RowPanels &, const bf16_t *, bf16_t *,
+                                               hipStream_t);
 template void launch_transpose_panels<float>(const RowPanels &, const float *, float *, hipStream_t);
 #define H2B_PANEL_INST(VT, XT, YT)                                                                      \
     template void launch_rowpanel<VT, XT, YT>(const RowPanels &, int, int, const VT *, const XT *, YT *, \

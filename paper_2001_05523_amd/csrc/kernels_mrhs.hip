@@ -261,14 +261,16 @@ __global__ void k_gather_mrhs(const int32_t *__restrict__ perm, int64_t n, int n
 }
 
 __global__ void k_scatter_mrhs(const int32_t *__restrict__ perm, int64_t n, int nb, int rb, double alpha,
-                               const double *__restrict__ yp, double *__restrict__ y, int64_t ldy)
+                               const double *__restrict__ yp, const double *__restrict__ yp2,
+                               double *__restrict__ y, int64_t ldy)
 {
     const int64_t tot = n * nb;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = e % n;
         const int r = (int)(e / n);
-        y[perm[k] + r * ldy] += alpha * yp[k * rb + r];
+        const double v = yp2 ? yp[k * rb + r] + yp2[k * rb + r] : yp[k * rb + r];
+        y[perm[k] + r * ldy] += alpha * v;
     }
 }
 
@@ -365,12 +367,12 @@ void launch_gather_mrhs(const int32_t *perm, int64_t n, int nb, int rb, const do
 }
 
 void launch_scatter_mrhs(const int32_t *perm, int64_t n, int nb, int rb, double alpha, const double *yp,
-                         double *y, int64_t ldy, hipStream_t st)
+                         const double *yp2, double *y, int64_t ldy, hipStream_t st)
 {
     check_rb(rb);
     if (nb < 1 || nb > rb) fail(H2B_EINVAL, "block holds 1..rb right-hand sides");
-    hipLaunchKernelGGL(k_scatter_mrhs, dim3(grid_for(n * nb)), dim3(NT), 0, st, perm, n, nb, rb, alpha, yp, y,
-                       ldy);
+    hipLaunchKernelGGL(k_scatter_mrhs, dim3(grid_for(n * nb)), dim3(NT), 0, st, perm, n, nb, rb, alpha, yp, yp2,
+                       y, ldy);
     hip_check(hipGetLastError(), "scatter launch");
 }
 

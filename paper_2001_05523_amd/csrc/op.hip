@@ -18,13 +18,14 @@ void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp)
     // output group per distinct input segment (keyed by its start), blocks in
     // order of appearance
     std::map<int, std::vector<int>> by_out;  // seg_in -> list of (group, segment)
-    std::map<int, int> out_len;
+    std::map<int, int> out_len, out_tag;
     std::vector<std::pair<int, int>> refs;
     for (int g = g0; g < g1; ++g)
         for (int s = rp.seg_ptr[g]; s < rp.seg_ptr[g + 1]; ++s) {
             if (rp.seg_len[s] == 0 || rp.nrows[g] == 0) continue;  // contributes nothing
             by_out[rp.seg_in[s]].push_back((int)refs.size());
             out_len[rp.seg_in[s]] = rp.seg_len[s];
+            out_tag[rp.seg_in[s]] = rp.seg_tag[s];
             refs.push_back({g, s});
         }
     // column offset of every segment inside its panel
@@ -39,6 +40,7 @@ void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp)
     for (auto &kv : by_out) {
         cp.out_begin.push_back(kv.first);
         cp.out_len.push_back(out_len[kv.first]);
+        cp.out_tag.push_back(out_tag[kv.first]);
         cp.max_out = std::max(cp.max_out, out_len[kv.first]);
         for (int ref : kv.second) {
             int g = refs[ref].first, s = refs[ref].second;
@@ -47,8 +49,19 @@ void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp)
             cp.b_c0.push_back(c0[s]);
             cp.b_nrows.push_back(rp.nrows[g]);
             cp.b_in.push_back(rp.out_begin[g]);
+            cp.b_tag.push_back(rp.group_tag[g]);
         }
         cp.blk_ptr.push_back((int32_t)cp.b_in.size());
+    }
+}
+
+void regroup_transposed(const ColPanels &cp, RowPanels &out)
+{
+    out = RowPanels();
+    for (int g = 0; g < cp.ngroups(); ++g) {
+        out.begin_group(cp.out_tag[g], cp.out_begin[g], cp.out_len[g]);
+        for (int b = cp.blk_ptr[g]; b < cp.blk_ptr[g + 1]; ++b) out.add_segment(cp.b_in[b], cp.b_nrows[b], cp.b_tag[b]);
+        out.end_group();
     }
 }
 
@@ -170,6 +183,9 @@ Op::~Op()
     for (auto &set : ev)
         for (auto &e : set)
             if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
 }
 
 static void upload_tree(Basis &B, hipStream_t st)
@@ -318,6 +334,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
         launch_coupling<bf16_t>(op->cpl, rax, cax, m, op->cpl_vals.as<bf16_t>(), st);
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
+    if (p.transposed_copy) make_transposed_copies(*op, st);
 
     // work vectors
     const size_t wsz = basis_size(p.farfield_dtype);
@@ -325,9 +342,39 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     const int64_t hmax = std::max(op->rowb->hat_total, op->colb->hat_total);
     op->xp.alloc(sizeof(double) * nmax);
     op->yp.alloc(sizeof(double) * nmax);
+    op->ypn.alloc(sizeof(double) * nmax);
+    hip_check(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking), "stream create");
+    hip_check(hipEventCreateWithFlags(&op->fork, hipEventDisableTiming), "event create");
+    hip_check(hipEventCreateWithFlags(&op->join, hipEventDisableTiming), "event create");
     op->xhat.alloc(wsz * std::max<int64_t>(hmax, 1));
     op->yhat.alloc(wsz * std::max<int64_t>(hmax, 1));
     return op;
+}
+
+void make_transposed_copies(Op &op, hipStream_t st)
+{
+    const h2b_dtype dt = op.params.farfield_dtype;
+    if (!op.has_R) {
+        regroup_transposed(op.near_T, op.near_R);
+        regroup_transposed(op.cpl_T, op.cpl_R);
+        op.near_R.upload(st);
+        op.cpl_R.upload(st);
+        op.near_R_vals.alloc(sizeof(double) * std::max<int64_t>(op.near_R.total, 1));
+        op.cpl_R_vals.alloc(coupling_size(dt) * std::max<int64_t>(op.cpl_R.total, 1));
+    }
+    launch_regroup_transpose<double>(op.near_T, op.near_R, op.near_vals.as<double>(), op.near_R_vals.as<double>(),
+                                     st);
+    if (dt == H2B_F64)
+        launch_regroup_transpose<double>(op.cpl_T, op.cpl_R, op.cpl_vals.as<double>(),
+                                         op.cpl_R_vals.as<double>(), st);
+    else if (dt == H2B_F32)
+        launch_regroup_transpose<float>(op.cpl_T, op.cpl_R, op.cpl_vals.as<float>(), op.cpl_R_vals.as<float>(),
+                                        st);
+    else
+        launch_regroup_transpose<bf16_t>(op.cpl_T, op.cpl_R, op.cpl_vals.as<bf16_t>(),
+                                         op.cpl_R_vals.as<bf16_t>(), st);
+    hip_check(hipStreamSynchronize(st), "transposed copies");
+    op.has_R = true;
 }
 
 // --------------------------------------------------------------- product
@@ -356,19 +403,41 @@ static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 }
 
 // Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
-// [4] after backward, [5] after nearfield, [6] after scatter.  The coupling and
-// nearfield phases each bracket exactly one kernel launch.
+// [4] after backward (caller's stream); [5] nearfield start, [6] nearfield end
+// (side stream); [7] after the join, [8] after scatter (caller's stream).  The
+// coupling and nearfield phases each bracket exactly one kernel launch.
 static hipEvent_t *event_set(Op &op, hipStream_t st)
 {
     if (!op.timing) return nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return nullptr;
     if (op.nev == op.ev.size()) {
-        std::array<hipEvent_t, 7> set{};
+        std::array<hipEvent_t, 9> set{};
         for (auto &e : set) hip_check(hipEventCreate(&e), "event create");
         op.ev.push_back(set);
     }
     return op.ev[op.nev++].data();
+}
+
+// Stream of the nearfield: the operator's side stream, which waits for
+// everything queued on st so far (fork), or st itself while st is being
+// captured into a graph (a captured product stays on the captured stream).
+static hipStream_t fork_side(Op &op, hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cs), "capture status");
+    if (cs != hipStreamCaptureStatusNone) return st;
+    hip_check(hipEventRecord(op.fork, st), "event record");
+    hip_check(hipStreamWaitEvent(op.side, op.fork, 0), "stream wait");
+    return op.side;
+}
+
+// st waits for everything queued on the nearfield stream ns so far (join).
+static void join_side(Op &op, hipStream_t ns, hipStream_t st)
+{
+    if (ns == st) return;
+    hip_check(hipEventRecord(op.join, ns), "event record");
+    hip_check(hipStreamWaitEvent(st, op.join, 0), "stream wait");
 }
 
 template <typename F, typename C>
@@ -378,37 +447,50 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     const Basis &Bout = trans ? *op.colb : *op.rowb;
     const int64_t nin = trans ? op.nrows : op.ncols;
     const int64_t nout = trans ? op.ncols : op.nrows;
-    double *xp = op.xp.as<double>(), *yp = op.yp.as<double>();
+    double *xp = op.xp.as<double>(), *yp = op.yp.as<double>(), *ypn = op.ypn.as<double>();
     F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
     hipEvent_t *ev = event_set(op, st);
-    auto mark = [&](int i) {
-        if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
+    auto mark = [&](int i, hipStream_t s) {
+        if (ev) hip_check(hipEventRecord(ev[i], s), "event record");
     };
     launch_fill_zero<F>(yhat, Bout.hat_total, st);
     launch_fill_zero<double>(yp, nout, st);
-    mark(0);
+    mark(0, st);
     launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
-    mark(1);
+    mark(1, st);
+    // nearfield into ypn on the side stream
+    hipStream_t ns = fork_side(op, st);
+    launch_fill_zero<double>(ypn, nout, ns);
+    mark(5, ns);
+    if (!trans)
+        launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
+                                                xp, ypn, true, ns, Role::Near);
+    else if (op.has_R)
+        launch_rowpanel<double, double, double>(op.near_R, 0, op.near_R.ngroups(), op.near_R_vals.as<double>(),
+                                                xp, ypn, true, ns, Role::Near);
+    else
+        launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
+                                                op.near_vals.as<double>(), xp, ypn, ns, Role::Near);
+    mark(6, ns);
+    // far field into yp on the caller's stream
     forward<F>(Bin, xp, xhat, st);
-    mark(2);
+    mark(2, st);
     if (!trans)
         launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, true, st,
+                                 Role::Coupling);
+    else if (op.has_R)
+        launch_rowpanel<C, F, F>(op.cpl_R, 0, op.cpl_R.ngroups(), op.cpl_R_vals.as<C>(), xhat, yhat, true, st,
                                  Role::Coupling);
     else
         launch_colpanel<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, st,
                                  Role::Coupling);
-    mark(3);
+    mark(3, st);
     backward<F>(Bout, yhat, yp, st);
-    mark(4);
-    if (!trans)
-        launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
-                                                xp, yp, true, st, Role::Near);
-    else
-        launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
-                                                op.near_vals.as<double>(), xp, yp, st, Role::Near);
-    mark(5);
-    launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, y, nout, st);
-    mark(6);
+    mark(4, st);
+    join_side(op, ns, st);
+    mark(7, st);
+    launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, ypn, y, nout, st);
+    mark(8, st);
 }
 
 // ------------------------------------------------ many right-hand sides
@@ -432,22 +514,24 @@ static void ensure_block_buffers(Op &op, int rb)
     op.ypb.alloc(sizeof(double) * nmax * rb);
     op.xhatb.alloc(fsz * hmax * rb);
     op.yhatb.alloc(fsz * hmax * rb);
+    op.ypbn.alloc(sizeof(double) * nmax * rb);
     op.mrhs_rb = rb;
 }
 
 template <typename F, typename C>
 static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *yhat, hipStream_t st)
 {
-    if (trans) {
+    if (trans && !op.has_R) {
         launch_colpanel_mrhs<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), rb, op.cpl_vals.as<C>(), xhat, yhat, true,
                                       st, Role::Coupling);
-    } else if constexpr (std::is_same<F, float>::value) {
-        launch_rowpanel_mrhs_mfma<C>(op.cpl, 0, op.cpl.ngroups(), rb, kc, op.cpl_vals.as<C>(), xhat, yhat, true,
-                                     st);
-    } else {
-        launch_rowpanel_mrhs<C, F, F>(op.cpl, 0, op.cpl.ngroups(), rb, op.cpl_vals.as<C>(), xhat, yhat, true, st,
-                                      Role::Coupling);
+        return;
     }
+    const RowPanels &P = trans ? op.cpl_R : op.cpl;
+    const C *vals = trans ? op.cpl_R_vals.as<C>() : op.cpl_vals.as<C>();
+    if constexpr (std::is_same<F, float>::value)
+        launch_rowpanel_mrhs_mfma<C>(P, 0, P.ngroups(), rb, kc, vals, xhat, yhat, true, st);
+    else
+        launch_rowpanel_mrhs<C, F, F>(P, 0, P.ngroups(), rb, vals, xhat, yhat, true, st, Role::Coupling);
 }
 
 // Product for nb <= rb right-hand sides at once (block vectors row-major).
@@ -459,40 +543,48 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
     const Basis &Bout = trans ? *op.colb : *op.rowb;
     const int64_t nin = trans ? op.nrows : op.ncols;
     const int64_t nout = trans ? op.ncols : op.nrows;
-    double *xp = op.xpb.as<double>(), *yp = op.ypb.as<double>();
+    double *xp = op.xpb.as<double>(), *yp = op.ypb.as<double>(), *ypn = op.ypbn.as<double>();
     F *xhat = op.xhatb.as<F>(), *yhat = op.yhatb.as<F>();
     hipEvent_t *ev = event_set(op, st);
-    auto mark = [&](int i) {
-        if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
+    auto mark = [&](int i, hipStream_t s) {
+        if (ev) hip_check(hipEventRecord(ev[i], s), "event record");
     };
     launch_fill_zero<F>(yhat, Bout.hat_total * rb, st);
     launch_fill_zero<double>(yp, nout * rb, st);
-    mark(0);
+    mark(0, st);
     launch_gather_mrhs(Bin.perm_dev, nin, nb, rb, x, ldx, xp, st);
-    mark(1);
+    mark(1, st);
+    hipStream_t ns = fork_side(op, st);
+    launch_fill_zero<double>(ypn, nout * rb, ns);
+    mark(5, ns);
+    if (!trans)
+        launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb, op.near_vals.as<double>(),
+                                                     xp, ypn, true, ns, Role::Near);
+    else if (op.has_R)
+        launch_rowpanel_mrhs<double, double, double>(op.near_R, 0, op.near_R.ngroups(), rb,
+                                                     op.near_R_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+    else
+        launch_colpanel_mrhs<double, double, double>(op.near_T, 0, op.near_T.ngroups(), rb,
+                                                     op.near_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+    mark(6, ns);
     launch_colpanel_mrhs<F, double, F>(Bin.leaf_F, 0, Bin.leaf_F.ngroups(), rb, Bin.leafT_vals.as<F>(), xp, xhat,
                                        false, st, Role::Leaf);
     for (auto &s : Bin.fw_steps)
         launch_colpanel_mrhs<F, F, F>(Bin.trans_F, s.first, s.second, rb, Bin.transT_vals.as<F>(), xhat, xhat,
                                       false, st, Role::Transfer);
-    mark(2);
+    mark(2, st);
     coupling_block<F, C>(op, trans, rb, op.tune_kc, xhat, yhat, st);
-    mark(3);
+    mark(3, st);
     for (auto &s : Bout.bw_steps)
         launch_colpanel_mrhs<F, F, F>(Bout.trans_T, s.first, s.second, rb, Bout.trans_vals.as<F>(), yhat, yhat,
                                       true, st, Role::Transfer);
     launch_colpanel_mrhs<F, F, double>(Bout.leaf_T, 0, Bout.leaf_T.ngroups(), rb, Bout.leaf_vals.as<F>(), yhat,
                                        yp, true, st, Role::Leaf);
-    mark(4);
-    if (!trans)
-        launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb, op.near_vals.as<double>(),
-                                                     xp, yp, true, st, Role::Near);
-    else
-        launch_colpanel_mrhs<double, double, double>(op.near_T, 0, op.near_T.ngroups(), rb,
-                                                     op.near_vals.as<double>(), xp, yp, true, st, Role::Near);
-    mark(5);
-    launch_scatter_mrhs(Bout.perm_dev, nout, nb, rb, alpha, yp, y, ldy, st);
-    mark(6);
+    mark(4, st);
+    join_side(op, ns, st);
+    mark(7, st);
+    launch_scatter_mrhs(Bout.perm_dev, nout, nb, rb, alpha, yp, ypn, y, ldy, st);
+    mark(8, st);
 }
 
 template <typename F, typename C>
@@ -596,18 +688,22 @@ void tune(Op &op, int nrhs, hipStream_t st, double *best_us)
     }
 }
 
-void phase_times(Op &op, double out[6])
+// Mean milliseconds per recorded product of gather, forward, coupling,
+// backward, nearfield (on the side stream, overlapping the far field),
+// scatter, and the whole product.
+void phase_times(Op &op, double out[7])
 {
     if (op.nev == 0) fail(H2B_ESTATE, "no timed product recorded (enable timing first)");
-    hip_check(hipEventSynchronize(op.ev[op.nev - 1][6]), "event sync");
-    for (int i = 0; i < 6; ++i) out[i] = 0.0;
+    hip_check(hipEventSynchronize(op.ev[op.nev - 1][8]), "event sync");
+    static const int from[7] = {0, 1, 2, 3, 5, 7, 0}, to[7] = {1, 2, 3, 4, 6, 8, 8};
+    for (int i = 0; i < 7; ++i) out[i] = 0.0;
     for (size_t k = 0; k < op.nev; ++k)
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 7; ++i) {
             float ms = 0.f;
-            hip_check(hipEventElapsedTime(&ms, op.ev[k][i], op.ev[k][i + 1]), "event time");
+            hip_check(hipEventElapsedTime(&ms, op.ev[k][from[i]], op.ev[k][to[i]]), "event time");
             out[i] += ms;
         }
-    for (int i = 0; i < 6; ++i) out[i] /= (double)op.nev;
+    for (int i = 0; i < 7; ++i) out[i] /= (double)op.nev;
     op.nev = 0;
 }
 
@@ -625,7 +721,10 @@ void op_stats(const Op &op, h2b_op_stats &s)
     s.bytes_near = op.near.total * 8;
     s.bytes_far = s.coupling_entries * (int64_t)coupling_size(op.params.farfield_dtype) +
                   (s.row_basis_entries + s.col_basis_entries) * (int64_t)basis_size(op.params.farfield_dtype);
-    s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.xhat.bytes + op.yhat.bytes);
+    s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.ypn.bytes + op.xhat.bytes + op.yhat.bytes);
+    s.bytes_transposed = op.has_R ? op.near_R.total * 8 + op.cpl_R.total *
+                                                              (int64_t)coupling_size(op.params.farfield_dtype)
+                                  : 0;
     s.row_coeffs = op.rowb->hat_total;
     s.col_coeffs = op.colb->hat_total;
     auto rk = [](const Basis &B, int32_t &mx, double &mean) {
@@ -696,6 +795,7 @@ void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, 
         transpose_basis_values(*B, op.params.farfield_dtype, st);
     }
     hip_check(hipStreamSynchronize(st), "geometry assembly");
+    if (op.has_R) make_transposed_copies(op, st);
 }
 
 // Leaf coefficients a(v) = backward transfers of S V^T v (the product

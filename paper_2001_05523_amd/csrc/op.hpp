@@ -50,13 +50,23 @@ struct Op {
     RowPanels cpl;
     ColPanels cpl_T;
     DevMem cpl_vals;
+    // Transposed copies grouped by column cluster (params.transposed_copy):
+    // A^T x then runs the row-panel kernels.
+    RowPanels near_R, cpl_R;
+    DevMem near_R_vals, cpl_R_vals;
+    bool has_R = false;
     DevMem xp, yp, xhat, yhat;              // product work vectors
-    DevMem xpb, ypb, xhatb, yhatb;          // block work vectors (many right-hand sides)
+    DevMem ypn;                             // near-field output (summed with yp by the scatter)
+    DevMem xpb, ypb, xhatb, yhatb, ypbn;    // block work vectors (many right-hand sides)
+    // The near field runs on its own stream beside the far field: forked
+    // after the gather, joined before the scatter.
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     DevMem gxp, gyp, gax, gay;              // shape-gradient work vectors
     int mrhs_rb = 0;                        // block width the block vectors are sized for
     int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)
     bool timing = false;
-    std::vector<std::array<hipEvent_t, 7>> ev;  // one event set per timed product
+    std::vector<std::array<hipEvent_t, 9>> ev;  // one event set per timed product
     size_t nev = 0;                              // timed products since timing was enabled
     ~Op();
 };
@@ -74,6 +84,8 @@ void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t 
 // Transposed copies of the leaf and transfer values (after they are final).
 void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
+// (Re)builds the transposed copies from the current nearfield and coupling values.
+void make_transposed_copies(Op &op, hipStream_t st);
 void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
                         int nrhs);
 // Allocates what a product with nrhs right-hand sides needs (before a capture).
@@ -93,7 +105,7 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
                                     const double *const *x, const int64_t *ldx, double *const *y,
                                     const int64_t *ldy, const int *nrhs, hipStream_t st);
 void batch_launch(Batch &b, hipStream_t st);
-void phase_times(Op &op, double out[6]);
+void phase_times(Op &op, double out[7]);
 void tune(Op &op, int nrhs, hipStream_t st, double *best_us);
 // Re-assembles the geometry-dependent parts (near field, leaf bases) for new
 // vertex coordinates with trees, boxes and interpolation points frozen.

@@ -160,6 +160,7 @@ struct ColPanels {
     std::vector<int32_t> out_begin, out_len, blk_ptr{0};
     std::vector<int64_t> b_val_off;
     std::vector<int32_t> b_stride, b_c0, b_nrows, b_in;
+    std::vector<int32_t> out_tag, b_tag;  // cluster ids of output groups and blocks (host only)
     int max_out = 0;
     ColPanelDev dev{};
     DevMem mem;
@@ -181,7 +182,11 @@ struct ColPanels {
 };
 
 // Column panels of the transposed product of groups [g0, g1) of rp: the output
-// groups are the distinct input segments, in order of first appearance.
+// groups are the distinct input segments, in increasing order of their start.
 void transpose_panels(const RowPanels &rp, int g0, int g1, ColPanels &cp);
+// Row panels of the transposed matrix described by cp (= transpose_panels of
+// some rp): one group per output group of cp, one segment per block, in cp's
+// order, so that value (i, j) of block b of rp lands at (j, i) of segment b.
+void regroup_transposed(const ColPanels &cp, RowPanels &out);
 
 }  // namespace h2b

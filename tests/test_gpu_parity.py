@@ -57,14 +57,16 @@ def _dense(s, kernel, q):
 
 @pytest.mark.parametrize("s,leaf", [(2, 8), (4, 8), (8, 32), (8, 13)])
 @pytest.mark.parametrize("kernel", ["slp", "dlp"])
-@pytest.mark.parametrize("trans", [False, True])
-def test_dense_parity_far_disabled(s, leaf, kernel, trans):
+@pytest.mark.parametrize("trans,copy", [(False, True), (True, True), (True, False)])
+def test_dense_parity_far_disabled(s, leaf, kernel, trans, copy):
     """H^2 disabled: every entry is a near-field quadrature value, so the GPU
-    product must equal the oracle's dense matrix to rounding (<= 1e-10)."""
+    product must equal the oracle's dense matrix to rounding (<= 1e-10).  The
+    transposed product is checked from the transposed copy and from the
+    column-wise read of the one copy."""
     h = _lib()
     v, t = synth.octa_sphere(s)
     q = 4
-    op = h.Operator(v, t, kernel=kernel, leaf=leaf, q_near=q, far_disabled=True)
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, q_near=q, far_disabled=True, transposed_copy=copy)
     A = _dense(s, kernel, q)
     nin = A.shape[0] if trans else A.shape[1]
     x = synth.random_vector(nin, 101)
@@ -250,6 +252,53 @@ def test_many_right_hand_sides(dtype, nrhs):
                 d = np.linalg.norm(Y[:, c] - y1) / np.linalg.norm(y1)
                 bound = {"f64": 1e-12, "f32": 1e-5, "bf16": 5e-3}[dtype]
                 assert d <= bound, (kernel, trans, c, d)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_transposed_copy_matches_column_read(dtype):
+    """A^T x from the transposed copies (row kernels) and from the column-wise
+    read of the single copy use the same stored values, so they agree to
+    rounding, for one vector and for a block of 16.  The BF16 block product
+    from the copy runs on matrix cores, which also round the cluster
+    coefficients to BF16: that bound is BF16's."""
+    h = _lib()
+    v, t = synth.octa_sphere(16)
+    bound = {"f64": 1e-13, "f32": 1e-6, "bf16": 1e-6}[dtype]
+    block_bound = {"f64": 1e-13, "f32": 1e-6, "bf16": 5e-3}[dtype]
+    for kernel in ("slp", "dlp"):
+        kw = dict(kernel=kernel, leaf=16, order_m=4, q_near=4, recompress_tol=1e-6, farfield_dtype=dtype)
+        a = h.Operator(v, t, transposed_copy=True, **kw)
+        b = h.Operator(v, t, transposed_copy=False, **kw)
+        assert a.info()["bytes_transposed"] > 0 and b.info()["bytes_transposed"] == 0
+        x = synth.random_vector(a.shape[0], 311)
+        ya, yb = _run(a, x, trans=True), _run(b, x, trans=True)
+        d = np.linalg.norm(ya - yb) / np.linalg.norm(yb)
+        assert d <= bound, (kernel, d)
+        X = synth.random_vector(a.shape[0], 312, cols=16)
+        Ya, Yb = _run_block(a, X, trans=True), _run_block(b, X, trans=True)
+        d = np.linalg.norm(Ya - Yb) / np.linalg.norm(Yb)
+        assert d <= block_bound, (kernel, "block", d)
+
+
+def test_phase_timing_brackets_the_product():
+    """Per-phase event timing with the nearfield on its own stream: every phase
+    lies inside the whole product, and timing does not change the result."""
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    op = h.Operator(v, t, kernel="dlp", leaf=16, order_m=3, q_near=4)
+    for trans in (False, True):
+        x = synth.random_vector(op.shape[0] if trans else op.shape[1], 321)
+        y0 = _run(op, x, trans=trans)
+        op.set_timing(True)
+        ys = [_run(op, x, trans=trans) for _ in range(3)]
+        ph = op.phase_times()
+        op.set_timing(False)
+        for y in ys:
+            assert np.array_equal(y, y0)
+        assert set(ph) == {"gather", "forward", "coupling", "backward", "nearfield", "scatter", "total"}
+        assert all(v > 0 for v in ph.values()), ph
+        far = ph["gather"] + ph["forward"] + ph["coupling"] + ph["backward"]
+        assert ph["total"] >= max(far, ph["nearfield"]) * (1 - 1e-6), ph
 
 
 def test_tuner_picks_a_tile_and_products_stay_exact():
