@@ -275,6 +275,13 @@ h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double
 h2b_status h2b_op_set_timing(h2b_op op, int enable);
 h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7]);
 
+/* Overlap of the nearfield with the far field (default 1).  With 0 every
+ * phase of the products of op runs on the caller's stream, one kernel after
+ * the other (for callers that schedule their own concurrent work, and for
+ * timing each kernel alone).  The result is the same either way.
+ * Errors: H2B_EINVAL if op is NULL. */
+h2b_status h2b_op_set_overlap(h2b_op op, int enable);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,7 @@ _SIGS = {
     "h2b_op_set_geometry": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "h2b_slp_shape_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "h2b_op_set_overlap": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
 }
 
@@ -259,6 +260,11 @@ class Operator:
 
     def set_timing(self, on=True):
         _check(h2b_op_set_timing(self.handle, int(bool(on))))
+
+    def set_overlap(self, on=True):
+        """Nearfield on its own stream beside the far field (default), or every
+        phase on the caller's stream."""
+        _check(h2b_op_set_overlap(self.handle, int(bool(on))))
 
     def phase_times(self):
         out = np.zeros(7)

@@ -287,6 +287,14 @@ h2b_status h2b_op_set_timing(h2b_op op, int enable)
     });
 }
 
+h2b_status h2b_op_set_overlap(h2b_op op, int enable)
+{
+    return guarded([&] {
+        need(op, "op");
+        op->op->overlap = enable != 0;
+    });
+}
+
 h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7])
 {
     return guarded([&] {

@@ -108,6 +108,12 @@ void launch_gather(const int32_t *perm, int64_t n, int nrhs, const double *x, in
 // y[perm[k] + c*ldy] += alpha * (yp[k + c*n] + yp2[k + c*n]); yp2 may be NULL
 void launch_scatter_add(const int32_t *perm, int64_t n, int nrhs, double alpha, const double *yp,
                         const double *yp2, double *y, int64_t ldy, hipStream_t st);
+// y[segment entry of column c] += sum_i P[i][c] * x[out_begin + i] for every
+// group P of rp in [g0, g1) (leaf and transfer roles; outputs of distinct
+// groups must be disjoint).
+template <typename VT, typename XT, typename YT>
+void launch_rowpanelT(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, hipStream_t st,
+                      Role role);
 // Transposed copy of the values `in` of the row panels that cp describes, as
 // the row panels `out` built by regroup_transposed(cp, out).
 template <typename T>

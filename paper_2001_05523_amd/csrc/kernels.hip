@@ -656,11 +656,33 @@ constexpr int CHUNK = 4096;  // largest number of input columns staged in LDS pe
 
 template <typename T> __device__ inline T stream_load(const T *p) { return __builtin_nontemporal_load(p); }
 
-// One workgroup of NW waves per group: stage the input segments of a column
-// chunk in LDS, then every wave takes two rows at a time and streams them with
-// coalesced non-temporal loads (8 in flight per lane); per-row partial sums
-// live in LDS across chunks.
-template <typename VT, typename XT, typename YT, int ROLE, int NW>
+// Segment descriptors of a group held in LDS by the row-panel kernel (groups
+// with more segments read them from global memory).
+template <int NW> constexpr int max_lds_segments() { return NW == 1 ? 128 : 512; }
+
+// Index of the segment holding panel column col: the last s in [0, n) with
+// c0[s] <= col (a zero-length segment shares its start with the next one).
+__device__ inline int find_segment(const int32_t *c0, int n, int col)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (c0[mid] <= col)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One workgroup of NW waves per group.  The group's segment descriptors go to
+// LDS; each column chunk of the input is gathered into LDS with every thread
+// issuing up to 8 independent loads (segment found by binary search), then
+// every wave takes RW rows at a time and streams them with coalesced
+// non-temporal loads (4 column blocks of 64 per row, 4*RW loads in flight per
+// lane); rows past the end repeat the last row, whose sums are dropped.
+// Per-row partial sums live in LDS across chunks.
+template <typename VT, typename XT, typename YT, int ROLE, int NW, int RW>
 __global__ __launch_bounds__(NW * 64) void k_rowpanel(RowPanelDev d, int g0, int chunk,
                                                       const VT *__restrict__ vals,
                                                       const XT *__restrict__ x, YT *__restrict__ y,
@@ -668,66 +690,74 @@ __global__ __launch_bounds__(NW * 64) void k_rowpanel(RowPanelDev d, int g0, int
 {
     using A = typename Acc<VT>::type;
     constexpr int NTH = NW * 64;
+    constexpr int MAXSEG = max_lds_segments<NW>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A *xs = reinterpret_cast<A *>(smem_raw);
     A *racc = xs + chunk;
+    __shared__ int32_t lds_c0[MAXSEG], lds_in[MAXSEG];
     const int g = g0 + blockIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
     const int64_t off = d.val_off[g];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sb = d.seg_ptr[g], nseg = d.seg_ptr[g + 1] - sb;
+    const int32_t *c0s = d.seg_c0 + sb, *ins = d.seg_in + sb;
+    if (nseg <= MAXSEG) {
+        for (int t = threadIdx.x; t < nseg; t += NTH) {
+            lds_c0[t] = c0s[t];
+            lds_in[t] = ins[t];
+        }
+        c0s = lds_c0;
+        ins = lds_in;
+    }
+    __syncthreads();
 
-    int seg = d.seg_ptr[g], seg_pos = 0;  // staging cursor over the segments
     for (int c0 = 0; c0 < nc; c0 += chunk) {
         const int clen = min(chunk, nc - c0);
-        {
-            int filled = 0;
-            int s = seg, p = seg_pos;
-            while (filled < clen) {
-                const int len = min(d.seg_len[s] - p, clen - filled);
-                const XT *src = x + d.seg_in[s] + p;
-                for (int j = threadIdx.x; j < len; j += NTH) xs[filled + j] = (A)src[j];
-                filled += len;
-                p += len;
-                if (p == d.seg_len[s]) {
-                    ++s;
-                    p = 0;
+        for (int e0 = threadIdx.x; e0 < clen; e0 += 8 * NTH) {
+            A v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = e0 + q * NTH;
+                v[q] = 0;
+                if (e < clen) {
+                    const int col = c0 + e;
+                    const int sg = find_segment(c0s, nseg, col);
+                    v[q] = (A)x[ins[sg] + (col - c0s[sg])];
                 }
             }
-            seg = s;
-            seg_pos = p;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (e0 + q * NTH < clen) xs[e0 + q * NTH] = v[q];
         }
         __syncthreads();
-        for (int r = 2 * wave; r < nr; r += 2 * NW) {
-            const VT *row0 = vals + off + (int64_t)r * nc + c0;
-            // an odd last row is paired with itself (the repeat hits in cache)
-            const VT *row1 = (r + 1 < nr) ? row0 + nc : row0;
-            A a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        for (int r = RW * wave; r < nr; r += RW * NW) {
+            A acc[RW][4];
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[i][k] = 0;
+            const VT *rows[RW];
+#pragma unroll
+            for (int i = 0; i < RW; ++i) rows[i] = vals + off + (int64_t)min(r + i, nr - 1) * nc + c0;
             int c = lane;
             for (; c + 192 < clen; c += 256) {
-                const VT p0 = stream_load(row0 + c), p1 = stream_load(row0 + c + 64);
-                const VT p2 = stream_load(row0 + c + 128), p3 = stream_load(row0 + c + 192);
-                const VT q0 = stream_load(row1 + c), q1 = stream_load(row1 + c + 64);
-                const VT q2 = stream_load(row1 + c + 128), q3 = stream_load(row1 + c + 192);
-                const A x0 = xs[c], x1 = xs[c + 64], x2 = xs[c + 128], x3 = xs[c + 192];
-                a0 += (A)p0 * x0;
-                a1 += (A)p1 * x1;
-                a2 += (A)p2 * x2;
-                a3 += (A)p3 * x3;
-                b0 += (A)q0 * x0;
-                b1 += (A)q1 * x1;
-                b2 += (A)q2 * x2;
-                b3 += (A)q3 * x3;
+                A xv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xv[k] = xs[c + 64 * k];
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) acc[i][k] += (A)stream_load(rows[i] + c + 64 * k) * xv[k];
             }
             for (; c < clen; c += 64) {
                 const A xv = xs[c];
-                a0 += (A)stream_load(row0 + c) * xv;
-                b0 += (A)stream_load(row1 + c) * xv;
+#pragma unroll
+                for (int i = 0; i < RW; ++i) acc[i][0] += (A)stream_load(rows[i] + c) * xv;
             }
-            const A sa = wave_sum((a0 + a1) + (a2 + a3));
-            const A sb = wave_sum((b0 + b1) + (b2 + b3));
-            if (lane == 0) {
-                racc[r] = (c0 == 0) ? sa : racc[r] + sa;
-                if (r + 1 < nr) racc[r + 1] = (c0 == 0) ? sb : racc[r + 1] + sb;
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+                const A sum = wave_sum((acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]));
+                if (lane == 0 && r + i < nr) racc[r + i] = (c0 == 0) ? sum : racc[r + i] + sum;
             }
         }
         __syncthreads();
@@ -944,7 +974,7 @@ __global__ __launch_bounds__(64) void k_rowpanel_narrow(RowPanelDev d, int g0, c
     }
 }
 
-template <typename VT, typename XT, typename YT, int ROLE, int NW>
+template <typename VT, typename XT, typename YT, int ROLE, int NW, int RW>
 static void rowpanel_nw(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, int acc,
                         hipStream_t st)
 {
@@ -952,8 +982,8 @@ static void rowpanel_nw(const RowPanels &rp, int g0, int g1, const VT *vals, con
     int chunk = std::min(CHUNK, std::max(64, (rp.max_ncols + 63) / 64 * 64));
     if (NW == 1) chunk = std::min(chunk, 1024);
     const size_t shm = sizeof(A) * ((size_t)chunk + (size_t)std::max(rp.max_nrows, 1));
-    hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, ROLE, NW>), dim3(g1 - g0), dim3(NW * 64), shm, st, rp.dev, g0,
-                       chunk, vals, x, y, acc);
+    hipLaunchKernelGGL((k_rowpanel<VT, XT, YT, ROLE, NW, RW>), dim3(g1 - g0), dim3(NW * 64), shm, st, rp.dev,
+                       g0, chunk, vals, x, y, acc);
 }
 
 template <typename VT, typename XT, typename YT, int ROLE>
@@ -961,8 +991,9 @@ static void rowpanel_role(const RowPanels &rp, int g0, int g1, const VT *vals, c
                           hipStream_t st)
 {
     // small panels (recompressed coupling, leaf and transfer matrices) get one
-    // wave per group so that many groups stream concurrently; tall panels
-    // (near field) share the staged input among four waves
+    // wave per group taking four rows at a time, so that many groups stream
+    // concurrently; tall panels (near field) share the staged input among four
+    // waves taking two rows each
     const double rows_per_group = (double)rp.total / std::max<int64_t>(1, (int64_t)rp.ngroups()) /
                                   std::max(1.0, (double)rp.max_ncols);
     if (rp.max_ncols <= 128 && (ROLE == 0 || ROLE == 1)) {
@@ -971,9 +1002,9 @@ static void rowpanel_role(const RowPanels &rp, int g0, int g1, const VT *vals, c
         return;
     }
     if (rp.max_nrows <= 32 || rows_per_group < 16)
-        rowpanel_nw<VT, XT, YT, ROLE, 1>(rp, g0, g1, vals, x, y, acc, st);
+        rowpanel_nw<VT, XT, YT, ROLE, 1, 4>(rp, g0, g1, vals, x, y, acc, st);
     else
-        rowpanel_nw<VT, XT, YT, ROLE, 4>(rp, g0, g1, vals, x, y, acc, st);
+        rowpanel_nw<VT, XT, YT, ROLE, 4, 2>(rp, g0, g1, vals, x, y, acc, st);
 }
 
 template <typename VT, typename XT, typename YT>
@@ -991,23 +1022,11 @@ void launch_rowpanel(const RowPanels &rp, int g0, int g1, const VT *vals, const 
     hip_check(hipGetLastError(), "row panel launch");
 }
 
-// sum_i col[i * stride] * v[i] with eight independent loads in flight.
-template <typename VT, typename XT, typename A>
-__device__ inline A column_dot(const VT *__restrict__ col, int64_t stride, const XT *__restrict__ v, int n)
-{
-    A a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int i = 0;
-    for (; i + 7 < n; i += 8) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] += (A)col[(i + q) * stride] * (A)v[i + q];
-    }
-    for (; i < n; ++i) a[0] += (A)col[i * stride] * (A)v[i];
-    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-}
-
 // Transposed product of narrow panels (leaf and transfer matrices): one wave per
-// output segment, lanes over its entries, rows of each block with eight loads
-// in flight; no cross-wave reduction.
+// output segment.  An output of ol <= 32 entries is covered S = 2 or 4 times
+// (lanes j + L*slice, L = 64/S lanes per slice), each slice taking every S-th
+// row of the blocks, so that more loads are in flight and each lane's chain is
+// S times shorter; the slices are summed with cross-lane shuffles.
 template <typename VT, typename XT, typename YT, int ROLE>
 __global__ __launch_bounds__(64) void k_colpanel_narrow(ColPanelDev d, int g0, const VT *__restrict__ vals,
                                                         const XT *__restrict__ x, YT *__restrict__ y,
@@ -1017,12 +1036,81 @@ __global__ __launch_bounds__(64) void k_colpanel_narrow(ColPanelDev d, int g0, c
     const int g = g0 + blockIdx.x;
     const int ob = d.out_begin[g], ol = d.out_len[g];
     const int b0 = d.blk_ptr[g], b1 = d.blk_ptr[g + 1];
-    for (int j = threadIdx.x; j < ol; j += 64) {
+    const int L = ol <= 16 ? 16 : ol <= 32 ? 32 : 64;
+    const int S = 64 / L;
+    const int lane = threadIdx.x, slice = lane / L;
+    for (int j0 = 0; j0 < ol; j0 += L) {
+        const int j = j0 + (lane % L);
+        const bool valid = j < ol;
         A acc = 0;
-        for (int b = b0; b < b1; ++b)
-            acc += column_dot<VT, XT, A>(vals + d.b_val_off[b] + d.b_c0[b] + j, d.b_stride[b], x + d.b_in[b],
-                                         d.b_nrows[b]);
-        y[ob + j] = accumulate ? (YT)((A)y[ob + j] + acc) : (YT)acc;
+        if (valid) {
+            for (int b = b0; b < b1; ++b) {
+                const VT *col = vals + d.b_val_off[b] + d.b_c0[b] + j;
+                const int64_t stride = d.b_stride[b];
+                const XT *v = x + d.b_in[b];
+                const int n = d.b_nrows[b];
+                A a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                int i = slice;
+                for (; i + 7 * S < n; i += 8 * S) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) a[q] += (A)col[(i + q * S) * stride] * (A)v[i + q * S];
+                }
+                for (; i < n; i += S) a[0] += (A)col[i * stride] * (A)v[i];
+                acc += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+            }
+        }
+        for (int o = L; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (valid && slice == 0) y[ob + j] = accumulate ? (YT)((A)y[ob + j] + acc) : (YT)acc;
+    }
+}
+
+// Transposed product of whole narrow panels (backward transformation through
+// leaf and transfer matrices): one wave per group, lanes over the panel's
+// columns, the group's input x[out_begin ..] (one entry per row) in LDS, 16
+// rows in flight; column c goes to the entry of its segment.  The outputs of
+// different groups are disjoint (children of distinct parents, distinct
+// leaves), so no reduction across groups is needed.  Invalid lanes (c >= nc)
+// read column 0 and discard the sum.
+template <typename VT, typename XT, typename YT, int ROLE>
+__global__ __launch_bounds__(64) void k_rowpanelT_narrow(RowPanelDev d, int g0, const VT *__restrict__ vals,
+                                                         const XT *__restrict__ x, YT *__restrict__ y)
+{
+    using A = typename Acc<VT>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    A *xs = reinterpret_cast<A *>(smem_raw);
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int64_t off = d.val_off[g];
+    const int lane = threadIdx.x;
+    const XT *xin = x + d.out_begin[g];
+    for (int i = lane; i < nr; i += 64) xs[i] = (A)xin[i];
+    __syncthreads();
+    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+        const int c = c0 + lane;
+        const bool valid = c < nc;
+        const VT *col = vals + off + (valid ? c : 0);
+        A a[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = 0;
+        // 16 rows per batch; the last batch is clamped to row nr-1 and weighted
+        // 0 past the end so that its loads are issued together
+        for (int i = 0; i < nr; i += 16) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = i + q, rr = min(r, nr - 1);
+                a[q] += (A)col[(int64_t)rr * nc] * (r < nr ? xs[rr] : A(0));
+            }
+        }
+        A acc = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc += a[q];
+        if (valid) {
+            int s = s0, sc = 0;
+            while (s + 1 < s1 && c >= sc + d.seg_len[s]) sc += d.seg_len[s++];
+            const int o = d.seg_in[s] + (c - sc);
+            y[o] = (YT)((A)y[o] + acc);
+        }
     }
 }
 
@@ -1088,6 +1176,22 @@ void launch_colpanel(const ColPanels &cp, int g0, int g1, const VT *vals, const 
     hip_check(hipGetLastError(), "column panel launch");
 }
 
+template <typename VT, typename XT, typename YT>
+void launch_rowpanelT(const RowPanels &rp, int g0, int g1, const VT *vals, const XT *x, YT *y, hipStream_t st,
+                      Role role)
+{
+    if (g1 <= g0) return;
+    using A = typename Acc<VT>::type;
+    const size_t shm = sizeof(A) * (size_t)std::max(rp.max_nrows, 1);
+    if (role == Role::Leaf)
+        hipLaunchKernelGGL((k_rowpanelT_narrow<VT, XT, YT, 0>), dim3(g1 - g0), dim3(64), shm, st, rp.dev, g0, vals,
+                           x, y);
+    else
+        hipLaunchKernelGGL((k_rowpanelT_narrow<VT, XT, YT, 1>), dim3(g1 - g0), dim3(64), shm, st, rp.dev, g0, vals,
+                           x, y);
+    hip_check(hipGetLastError(), "transposed row panel launch");
+}
+
 template <typename T>
 void launch_regroup_transpose(const ColPanels &cp, const RowPanels &out, const T *in, T *o, hipStream_t st)
 {
@@ -1148,6 +1252,12 @@ template void launch_leaf_grad<float>(const RowPanels &, const int32_t *, const 
                                       const double *, double *, double *, double *, hipStream_t);
 template void launch_fill_zero<float>(float *, int64_t, hipStream_t);
 template void launch_transpose_panels<double>(const RowPanels &, const double *, double *, hipStream_t);
+template void launch_rowpanelT<double, double, double>(const RowPanels &, int, int, const double *,
+                                                      const double *, double *, hipStream_t, Role);
+template void launch_rowpanelT<float, float, float>(const RowPanels &, int, int, const float *, const float *,
+                                                   float *, hipStream_t, Role);
+template void launch_rowpanelT<float, float, double>(const RowPanels &, int, int, const float *, const float *,
+                                                    double *, hipStream_t, Role);
 template void launch_regroup_transpose<double>(const ColPanels &, const RowPanels &, const double *, double *,
                                                hipStream_t);
 template void launch_regroup_transpose<float>(const ColPanels &, const RowPanels &, const float *, float *,

@@ -395,11 +395,10 @@ static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
 template <typename F>
 static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 {
-    for (auto &s : B.bw_steps)
-        launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), yhat, yhat, st,
-                                 Role::Transfer);
-    launch_colpanel<F, F, double>(B.leaf_T, 0, B.leaf_T.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st,
-                                  Role::Leaf);
+    for (auto it = B.fw_steps.rbegin(); it != B.fw_steps.rend(); ++it)
+        launch_rowpanelT<F, F, F>(B.trans, it->first, it->second, B.trans_vals.as<F>(), yhat, yhat, st,
+                                  Role::Transfer);
+    launch_rowpanelT<F, F, double>(B.leaf, 0, B.leaf.ngroups(), B.leaf_vals.as<F>(), yhat, yp, st, Role::Leaf);
 }
 
 // Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
@@ -420,10 +419,12 @@ static hipEvent_t *event_set(Op &op, hipStream_t st)
 }
 
 // Stream of the nearfield: the operator's side stream, which waits for
-// everything queued on st so far (fork), or st itself while st is being
-// captured into a graph (a captured product stays on the captured stream).
+// everything queued on st so far (fork), or st itself when overlap is off or
+// while st is being captured into a graph (a captured product stays on the
+// captured stream).
 static hipStream_t fork_side(Op &op, hipStream_t st)
 {
+    if (!op.overlap) return st;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hip_check(hipStreamIsCapturing(st, &cs), "capture status");
     if (cs != hipStreamCaptureStatusNone) return st;
@@ -458,20 +459,24 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     mark(0, st);
     launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
     mark(1, st);
-    // nearfield into ypn on the side stream
+    // nearfield into ypn: on the side stream from here, or on st after the
+    // backward transformation
     hipStream_t ns = fork_side(op, st);
-    launch_fill_zero<double>(ypn, nout, ns);
-    mark(5, ns);
-    if (!trans)
-        launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(),
-                                                xp, ypn, true, ns, Role::Near);
-    else if (op.has_R)
-        launch_rowpanel<double, double, double>(op.near_R, 0, op.near_R.ngroups(), op.near_R_vals.as<double>(),
-                                                xp, ypn, true, ns, Role::Near);
-    else
-        launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(),
-                                                op.near_vals.as<double>(), xp, ypn, ns, Role::Near);
-    mark(6, ns);
+    auto nearfield = [&] {
+        launch_fill_zero<double>(ypn, nout, ns);
+        mark(5, ns);
+        if (!trans)
+            launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(), xp,
+                                                    ypn, true, ns, Role::Near);
+        else if (op.has_R)
+            launch_rowpanel<double, double, double>(op.near_R, 0, op.near_R.ngroups(),
+                                                    op.near_R_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+        else
+            launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(), op.near_vals.as<double>(),
+                                                    xp, ypn, ns, Role::Near);
+        mark(6, ns);
+    };
+    if (ns != st) nearfield();
     // far field into yp on the caller's stream
     forward<F>(Bin, xp, xhat, st);
     mark(2, st);
@@ -487,6 +492,7 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     mark(3, st);
     backward<F>(Bout, yhat, yp, st);
     mark(4, st);
+    if (ns == st) nearfield();
     join_side(op, ns, st);
     mark(7, st);
     launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, ypn, y, nout, st);
@@ -555,18 +561,21 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
     launch_gather_mrhs(Bin.perm_dev, nin, nb, rb, x, ldx, xp, st);
     mark(1, st);
     hipStream_t ns = fork_side(op, st);
-    launch_fill_zero<double>(ypn, nout * rb, ns);
-    mark(5, ns);
-    if (!trans)
-        launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb, op.near_vals.as<double>(),
-                                                     xp, ypn, true, ns, Role::Near);
-    else if (op.has_R)
-        launch_rowpanel_mrhs<double, double, double>(op.near_R, 0, op.near_R.ngroups(), rb,
-                                                     op.near_R_vals.as<double>(), xp, ypn, true, ns, Role::Near);
-    else
-        launch_colpanel_mrhs<double, double, double>(op.near_T, 0, op.near_T.ngroups(), rb,
-                                                     op.near_vals.as<double>(), xp, ypn, true, ns, Role::Near);
-    mark(6, ns);
+    auto nearfield = [&] {
+        launch_fill_zero<double>(ypn, nout * rb, ns);
+        mark(5, ns);
+        if (!trans)
+            launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb,
+                                                         op.near_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+        else if (op.has_R)
+            launch_rowpanel_mrhs<double, double, double>(op.near_R, 0, op.near_R.ngroups(), rb,
+                                                         op.near_R_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+        else
+            launch_colpanel_mrhs<double, double, double>(op.near_T, 0, op.near_T.ngroups(), rb,
+                                                         op.near_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+        mark(6, ns);
+    };
+    if (ns != st) nearfield();
     launch_colpanel_mrhs<F, double, F>(Bin.leaf_F, 0, Bin.leaf_F.ngroups(), rb, Bin.leafT_vals.as<F>(), xp, xhat,
                                        false, st, Role::Leaf);
     for (auto &s : Bin.fw_steps)
@@ -581,6 +590,7 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
     launch_colpanel_mrhs<F, F, double>(Bout.leaf_T, 0, Bout.leaf_T.ngroups(), rb, Bout.leaf_vals.as<F>(), yhat,
                                        yp, true, st, Role::Leaf);
     mark(4, st);
+    if (ns == st) nearfield();
     join_side(op, ns, st);
     mark(7, st);
     launch_scatter_mrhs(Bout.perm_dev, nout, nb, rb, alpha, yp, ypn, y, ldy, st);

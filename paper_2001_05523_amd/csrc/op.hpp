@@ -62,6 +62,7 @@ struct Op {
     // after the gather, joined before the scatter.
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    bool overlap = true;                    // false: the nearfield stays on the caller's stream
     DevMem gxp, gyp, gax, gay;              // shape-gradient work vectors
     int mrhs_rb = 0;                        // block width the block vectors are sized for
     int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)

@@ -96,6 +96,7 @@ struct Packer {
 struct RowPanelDev {
     const int64_t *val_off;
     const int32_t *nrows, *ncols, *out_begin, *seg_ptr, *seg_in, *seg_len;
+    const int32_t *seg_c0;         // column of each segment inside its group's panel
     const int32_t *tag, *seg_tag;  // cluster ids of groups and segments (assembly only)
 };
 
@@ -108,6 +109,7 @@ struct ColPanelDev {
 struct RowPanels {
     std::vector<int64_t> val_off;
     std::vector<int32_t> nrows, ncols, out_begin, seg_ptr{0}, seg_in, seg_len;
+    std::vector<int32_t> seg_c0;     // column of each segment inside its group's panel
     std::vector<int32_t> group_tag;  // cluster id of each group
     std::vector<int32_t> seg_tag;    // cluster id of each segment
     int64_t total = 0;               // number of stored values
@@ -130,6 +132,7 @@ struct RowPanels {
         seg_tag.push_back(tag);
         seg_in.push_back(in);
         seg_len.push_back(len);
+        seg_c0.push_back(ncols.back());
         ncols.back() += len;
     }
     void end_group()
@@ -150,6 +153,7 @@ struct RowPanels {
         pk.add(seg_ptr, const_cast<int32_t **>(&dev.seg_ptr));
         pk.add(seg_in, const_cast<int32_t **>(&dev.seg_in));
         pk.add(seg_len, const_cast<int32_t **>(&dev.seg_len));
+        pk.add(seg_c0, const_cast<int32_t **>(&dev.seg_c0));
         pk.add(group_tag, const_cast<int32_t **>(&dev.tag));
         pk.add(seg_tag, const_cast<int32_t **>(&dev.seg_tag));
         pk.upload(mem, st);

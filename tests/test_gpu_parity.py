@@ -299,6 +299,16 @@ def test_phase_timing_brackets_the_product():
         assert all(v > 0 for v in ph.values()), ph
         far = ph["gather"] + ph["forward"] + ph["coupling"] + ph["backward"]
         assert ph["total"] >= max(far, ph["nearfield"]) * (1 - 1e-6), ph
+        # every phase on the caller's stream: same result, phases in sequence
+        op.set_overlap(False)
+        op.set_timing(True)
+        y1 = _run(op, x, trans=trans)
+        ph = op.phase_times()
+        op.set_timing(False)
+        op.set_overlap(True)
+        assert np.array_equal(y1, y0)
+        far = ph["gather"] + ph["forward"] + ph["coupling"] + ph["backward"]
+        assert ph["total"] >= far + ph["nearfield"] + ph["scatter"] - 1e-3, ph
 
 
 def test_tuner_picks_a_tile_and_products_stay_exact():
