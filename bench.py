@@ -28,7 +28,7 @@ import numpy as np
 METRIC = "H² G/K matvec ms & HBM GB/s at 2M triangles; mixed vs FP64 at rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["kernels.hip", "op.hip", "recompress.hip", "panels.hpp", "device.hpp", "op.hpp"]
+KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "op.hip", "recompress.hip", "panels.hpp", "device.hpp", "op.hpp"]
 
 
 def sources_digest():
@@ -67,11 +67,27 @@ def alg_bytes(info, fsz, trans=False):
     nin, nout = (info["rows"], info["cols"]) if trans else (info["cols"], info["rows"])
     hin, hout = (info["row_coeffs"], info["col_coeffs"]) if trans else (info["col_coeffs"], info["row_coeffs"])
     vec = 8 * (nout + 2 * nout + nin)  # gather/scatter/x/y
-    near = 8 * info["near_entries"] + 8 * (nin + 2 * nout)
+    if info["near_sym_entries"] > 0:
+        # once-per-pair storage: entries, column sums written and read back,
+        # corrections (value, index, gathered x), their row pointers
+        near = (8 * info["near_sym_entries"] + 16 * info["near_sym_columns"]
+                + 20 * info["near_sym_corrections"] + 8 * nout + 8 * (nin + 2 * nout))
+    else:
+        near = 8 * info["near_entries"] + 8 * (nin + 2 * nout)
     cpl = fsz * info["coupling_entries"] + fsz * (hin + 2 * hout)
     bases = fsz * (info["row_basis_entries"] + info["col_basis_entries"])
     total = near + cpl + bases + vec
     return dict(total=total, near=near, coupling=cpl, bases=bases)
+
+
+def kernel_name(op, phase, info):
+    """Kernels that make up a product phase, for the roofline record."""
+    if phase == "coupling":
+        return "%s coupling, A x and A^T x launches (k_rowpanel<double, double, double, 2, 1, 4>)" % op
+    if info["near_sym_entries"] > 0:
+        return ("%s nearfield stored once per pair of leaves, A x and A^T x launches (k_nearsym<false|true> "
+                "+ k_symreduce)" % op)
+    return "%s nearfield, A x and A^T x launches (k_rowpanel<double, double, double, 3, 4, 2>)" % op
 
 
 def time_steps(torch, items, steps, warmup):
@@ -275,8 +291,7 @@ def main():
         "step_gbps": round(step_bytes[""] / ms64 / 1e6, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "%s %s panel product, A x and A^T x launches (k_rowpanel<double, double, double, %d, *>)"
-                      % (dominant[0], dominant[1], 2 if dominant[1] == "coupling" else 3),
+            "kernel": kernel_name(dominant[0], dominant[1], ops[dominant[0]].info()),
             "achieved": round(dominant[3] / dominant[2] / 1e6, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -144,10 +144,15 @@ typedef struct {
     int transposed_copy;    /* 1: also store the nearfield and coupling matrices transposed and
                                grouped by column cluster, so that A^T x streams rows like A x
                                (twice that storage); 0: A^T x reads the one copy by columns */
+    int symmetric_near;     /* 1: for G on one cluster tree (rows == cols) also store every pair of
+                               nearfield leaves once (N_tt and N_ts, s > t) plus the sparse
+                               difference G_ji - G_ij of the touching pairs across leaves; the
+                               single-vector products G x and G^T x then read about half the
+                               nearfield bytes (0.53x the nearfield storage extra) */
 } h2b_params;
 
 /* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64,
- * transposed_copy 1. */
+ * transposed_copy 1, symmetric_near 1. */
 void h2b_params_default(h2b_params *p);
 
 /* Assembles G (kernel H2B_SLP, cols tree P0) or K (H2B_DLP, cols tree P1) on
@@ -178,6 +183,9 @@ typedef struct {
     int32_t max_rank_row, max_rank_col;
     double mean_rank_row, mean_rank_col;
     int64_t bytes_transposed;      /* device bytes of the transposed copies (0 if none) */
+    int64_t near_sym_entries;      /* entries of the once-per-pair nearfield (0 if none) */
+    int64_t near_sym_columns;      /* its panel columns (one column sum each per product) */
+    int64_t near_sym_corrections;  /* touching pairs across leaves (corrections per product) */
 } h2b_op_stats;
 
 h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
@@ -270,8 +278,9 @@ h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double
  * recorded product and returns the mean milliseconds per product of
  * phases[0..6] = gather, forward transformation, coupling, backward
  * transformation, nearfield, scatter, whole product, then restarts the
- * average.  The coupling and nearfield phases each contain exactly one kernel
- * launch.  Errors: H2B_ESTATE if nothing was recorded. */
+ * average.  The coupling phase contains one kernel launch, the nearfield
+ * phase one (two with the once-per-pair storage of G: the panel pass and the
+ * reduction of its column sums).  Errors: H2B_ESTATE if nothing was recorded. */
 h2b_status h2b_op_set_timing(h2b_op op, int enable);
 h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7]);
 

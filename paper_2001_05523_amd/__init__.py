@@ -40,7 +40,7 @@ _P = ctypes.POINTER
 class h2b_params(ctypes.Structure):
     _fields_ = [("order_m", ctypes.c_int), ("q_near", ctypes.c_int),
                 ("recompress_tol", ctypes.c_double), ("farfield_dtype", ctypes.c_int),
-                ("transposed_copy", ctypes.c_int)]
+                ("transposed_copy", ctypes.c_int), ("symmetric_near", ctypes.c_int)]
 
 
 class h2b_op_stats(ctypes.Structure):
@@ -50,7 +50,8 @@ class h2b_op_stats(ctypes.Structure):
                 ("bytes_near", _i64), ("bytes_far", _i64), ("bytes_vectors", _i64),
                 ("row_coeffs", _i64), ("col_coeffs", _i64),
                 ("max_rank_row", _i32), ("max_rank_col", _i32),
-                ("mean_rank_row", _dbl), ("mean_rank_col", _dbl), ("bytes_transposed", _i64)]
+                ("mean_rank_row", _dbl), ("mean_rank_col", _dbl), ("bytes_transposed", _i64),
+                ("near_sym_entries", _i64), ("near_sym_columns", _i64), ("near_sym_corrections", _i64)]
 
 
 _SIGS = {
@@ -198,14 +199,15 @@ class Operator:
 
     def __init__(self, verts=None, tris=None, kernel="slp", leaf=32, order_m=4, q_near=4,
                  eta=1.0, far_disabled=False, recompress_tol=0.0, farfield_dtype="f64",
-                 transposed_copy=True, stream=None, mesh=None):
+                 transposed_copy=True, symmetric_near=True, stream=None, mesh=None):
         self.mesh = mesh if mesh is not None else Mesh(verts, tris)
         self.kernel = H2B_SLP if kernel == "slp" else H2B_DLP
         self.rows = Tree(self.mesh, H2B_P0, leaf)
         self.cols = self.rows if self.kernel == H2B_SLP else Tree(self.mesh, H2B_P1, leaf)
         self.blocks = Blocks(self.rows, self.cols, eta, far_disabled)
         p = default_params(order_m=order_m, q_near=q_near, recompress_tol=recompress_tol,
-                           farfield_dtype=_DTYPES[farfield_dtype], transposed_copy=int(bool(transposed_copy)))
+                           farfield_dtype=_DTYPES[farfield_dtype], transposed_copy=int(bool(transposed_copy)),
+                           symmetric_near=int(bool(symmetric_near)))
         h = _vp()
         _check(h2b_assemble(self.blocks.handle, self.kernel, ctypes.byref(p), _stream_ptr(stream),
                             ctypes.byref(h)))

@@ -335,6 +335,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
     if (p.transposed_copy) make_transposed_copies(*op, st);
+    if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols) make_symmetric_near(*op, st);
 
     // work vectors
     const size_t wsz = basis_size(p.farfield_dtype);
@@ -404,7 +405,8 @@ static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 // Events: [0] start, [1] after gather, [2] after forward, [3] after coupling,
 // [4] after backward (caller's stream); [5] nearfield start, [6] nearfield end
 // (side stream); [7] after the join, [8] after scatter (caller's stream).  The
-// coupling and nearfield phases each bracket exactly one kernel launch.
+// coupling phase brackets one kernel launch, the nearfield phase one (two for
+// the once-per-pair storage of G: rows and column sums, then their reduction).
 static hipEvent_t *event_set(Op &op, hipStream_t st)
 {
     if (!op.timing) return nullptr;
@@ -465,7 +467,9 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     auto nearfield = [&] {
         launch_fill_zero<double>(ypn, nout, ns);
         mark(5, ns);
-        if (!trans)
+        if (op.sym)
+            symmetric_near_product(op, trans, xp, ypn, ns);
+        else if (!trans)
             launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(), xp,
                                                     ypn, true, ns, Role::Near);
         else if (op.has_R)
@@ -732,6 +736,11 @@ void op_stats(const Op &op, h2b_op_stats &s)
     s.bytes_far = s.coupling_entries * (int64_t)coupling_size(op.params.farfield_dtype) +
                   (s.row_basis_entries + s.col_basis_entries) * (int64_t)basis_size(op.params.farfield_dtype);
     s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.ypn.bytes + op.xhat.bytes + op.yhat.bytes);
+    if (op.sym) {
+        s.near_sym_entries = op.sym->P.total;
+        s.near_sym_columns = op.sym->col_base.back();
+        s.near_sym_corrections = op.sym->ncorr;
+    }
     s.bytes_transposed = op.has_R ? op.near_R.total * 8 + op.cpl_R.total *
                                                               (int64_t)coupling_size(op.params.farfield_dtype)
                                   : 0;
@@ -806,6 +815,7 @@ void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, 
     }
     hip_check(hipStreamSynchronize(st), "geometry assembly");
     if (op.has_R) make_transposed_copies(op, st);
+    if (op.sym) make_symmetric_near(op, st);
 }
 
 // Leaf coefficients a(v) = backward transfers of S V^T v (the product

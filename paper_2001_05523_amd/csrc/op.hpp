@@ -36,6 +36,35 @@ struct Basis {
     const int32_t *perm_dev = nullptr;
 };
 
+// Nearfield of G on one cluster tree stored once per pair of leaves: for every
+// row leaf t the panel [N_tt | N_ts for the nearfield leaves s > t].  The
+// product reads each off-diagonal block once for both y_t += N_ts x_s and
+// y_s += N_ts^T x_t; the column sums go to `scratch` and are added per leaf by
+// a second launch, which also applies the sparse correction of the touching
+// pairs across leaves, whose two quadratures agree only to quadrature error
+// (G_ji - G_ij, stored for G x by row j and for G^T x by row i).
+struct SymNear {
+    RowPanels P;                    // groups = row leaves, segment 0 = the diagonal block
+    DevMem vals;
+    DevMem scratch;                 // one column sum per panel column
+    std::vector<int64_t> col_base;  // first scratch entry of each group
+    ColPanels red;                  // per leaf u: the blocks (t, u), t != u, as scratch offsets
+    // copy of the stored blocks out of the full nearfield
+    std::vector<int64_t> cp_src, cp_dst;
+    std::vector<int32_t> cp_src_ld, cp_dst_ld, cp_rows, cp_cols;
+    // corrections: CSR over cluster-ordered rows, for G x (fwd) and G^T x (bwd)
+    std::vector<int64_t> cf_ptr, cb_ptr;
+    std::vector<int32_t> cf_idx, cb_idx;
+    std::vector<int64_t> cf_a, cf_b, cb_a, cb_b;  // value = near[a] - near[b]
+    DevMem desc, cf_val, cb_val;
+    const int64_t *d_col_base = nullptr, *d_cp_src = nullptr, *d_cp_dst = nullptr;
+    const int32_t *d_cp_src_ld = nullptr, *d_cp_dst_ld = nullptr, *d_cp_rows = nullptr, *d_cp_cols = nullptr;
+    const int64_t *d_cf_ptr = nullptr, *d_cb_ptr = nullptr, *d_cf_a = nullptr, *d_cf_b = nullptr;
+    const int64_t *d_cb_a = nullptr, *d_cb_b = nullptr;
+    const int32_t *d_cf_idx = nullptr, *d_cb_idx = nullptr;
+    int64_t ncorr = 0;
+};
+
 struct Op {
     std::shared_ptr<const Blocks> blocks;
     h2b_kernel kernel = H2B_SLP;
@@ -55,6 +84,7 @@ struct Op {
     RowPanels near_R, cpl_R;
     DevMem near_R_vals, cpl_R_vals;
     bool has_R = false;
+    std::unique_ptr<SymNear> sym;           // params.symmetric_near for G on one tree
     DevMem xp, yp, xhat, yhat;              // product work vectors
     DevMem ypn;                             // near-field output (summed with yp by the scatter)
     DevMem xpb, ypb, xhatb, yhatb, ypbn;    // block work vectors (many right-hand sides)
@@ -87,6 +117,10 @@ void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
 // (Re)builds the transposed copies from the current nearfield and coupling values.
 void make_transposed_copies(Op &op, hipStream_t st);
+// Structure (first call) and values of the once-per-pair nearfield of G.
+void make_symmetric_near(Op &op, hipStream_t st);
+// ypn += N x (trans = 0) or N^T x (trans = 1) from the once-per-pair storage.
+void symmetric_near_product(const Op &op, int trans, const double *xp, double *ypn, hipStream_t st);
 void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
                         int nrhs);
 // Allocates what a product with nrhs right-hand sides needs (before a capture).

@@ -280,6 +280,27 @@ def test_transposed_copy_matches_column_read(dtype):
         assert d <= block_bound, (kernel, "block", d)
 
 
+@pytest.mark.parametrize("far_disabled,tol", [(True, 0.0), (False, 1e-6)])
+def test_once_per_pair_nearfield_matches_full(far_disabled, tol):
+    """G x and G^T x from the nearfield stored once per pair of leaves (plus
+    the corrections of the touching pairs across leaves) equal the products
+    from the full nearfield to rounding; sizes span several leaves and a
+    ragged last leaf (leaf 13)."""
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    kw = dict(kernel="slp", leaf=13, order_m=3, q_near=4, far_disabled=far_disabled, recompress_tol=tol)
+    a = h.Operator(v, t, symmetric_near=True, **kw)
+    b = h.Operator(v, t, symmetric_near=False, **kw)
+    ia, ib = a.info(), b.info()
+    assert ia["near_sym_entries"] > 0 and ib["near_sym_entries"] == 0
+    assert ia["near_sym_entries"] < 0.75 * ia["near_entries"]
+    assert ia["near_sym_corrections"] > 0
+    for trans in (False, True):
+        x = synth.random_vector(a.shape[0], 331 + trans)
+        ya, yb = _run(a, x, trans=trans), _run(b, x, trans=trans)
+        assert _maxrel(ya, yb) <= 1e-13, (trans, _maxrel(ya, yb))
+
+
 def test_phase_timing_brackets_the_product():
     """Per-phase event timing with the nearfield on its own stream: every phase
     lies inside the whole product, and timing does not change the result."""
