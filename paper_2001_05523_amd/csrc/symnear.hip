@@ -52,11 +52,12 @@ __device__ inline int find_seg(const int32_t *c0, int n, int col)
 // One workgroup of 4 waves per row leaf t.  Input columns are gathered into
 // LDS (x of the column segments; for G^T x the diagonal columns are set to 0,
 // because the diagonal block enters transposed, through its column sums).
-// Each wave streams two rows at a time with coalesced non-temporal loads; the
-// products feed the row sums (wave reductions) and, weighted by x_t of the two
-// rows, the column sums in LDS (ds_add_f64).  Column sums of the diagonal
-// block go to y_t for G^T x and are dropped for G x; the others go to the
-// scratch vector.
+// Each wave streams two rows at a time with coalesced non-temporal loads, 4
+// column blocks of 64 per step and the last < 4 blocks issued together under
+// per-lane predicates; the products feed the row sums (wave reductions) and,
+// weighted by x_t of the two rows, the column sums in LDS (ds_add_f64).
+// Column sums of the diagonal block go to y_t for G^T x and are dropped for
+// G x; the others go to the scratch vector.
 template <bool TRANS>
 __global__ __launch_bounds__(SYM_NW * 64) void k_nearsym(RowPanelDev d, int chunk, const double *__restrict__ vals,
                                                          const double *__restrict__ x, double *__restrict__ y,
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(SYM_NW * 64) void k_nearsym(RowPanelDev d, int chun
                                                          const int64_t *__restrict__ col_base)
 {
     constexpr int NTH = SYM_NW * 64;
+    constexpr int NB = 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *xs = reinterpret_cast<double *>(smem_raw);  // chunk
     double *cs = xs + chunk;                            // chunk
@@ -118,30 +120,40 @@ __global__ __launch_bounds__(SYM_NW * 64) void k_nearsym(RowPanelDev d, int chun
             const double *row0 = vals + off + (int64_t)r * nc + c0;
             const double *row1 = two ? row0 + nc : row0;
             const double w0 = xt[r], w1 = two ? xt[r + 1] : 0.0;
-            double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+            double a[NB] = {0, 0, 0, 0}, b[NB] = {0, 0, 0, 0};
             int c = lane;
-            for (; c + 192 < clen; c += 256) {
-                double p[4], q[4];
+            for (; c + 64 * (NB - 1) < clen; c += 64 * NB) {
+                double p[NB], q[NB];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     p[k] = __builtin_nontemporal_load(row0 + c + 64 * k);
                     q[k] = __builtin_nontemporal_load(row1 + c + 64 * k);
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < NB; ++k) {
                     const double xv = xs[c + 64 * k];
                     a[k] += p[k] * xv;
                     b[k] += q[k] * xv;
                     atomicAdd(&cs[c + 64 * k], p[k] * w0 + q[k] * w1);
                 }
             }
-            for (; c < clen; c += 64) {
-                const double p = __builtin_nontemporal_load(row0 + c);
-                const double q = __builtin_nontemporal_load(row1 + c);
-                const double xv = xs[c];
-                a[0] += p * xv;
-                b[0] += q * xv;
-                atomicAdd(&cs[c], p * w0 + q * w1);
+            if (c < clen) {  // fewer than NB blocks left
+                double p[NB - 1], q[NB - 1];
+#pragma unroll
+                for (int k = 0; k < NB - 1; ++k) {
+                    const bool in = c + 64 * k < clen;
+                    p[k] = in ? __builtin_nontemporal_load(row0 + c + 64 * k) : 0.0;
+                    q[k] = in ? __builtin_nontemporal_load(row1 + c + 64 * k) : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < NB - 1; ++k) {
+                    if (c + 64 * k < clen) {
+                        const double xv = xs[c + 64 * k];
+                        a[k] += p[k] * xv;
+                        b[k] += q[k] * xv;
+                        atomicAdd(&cs[c + 64 * k], p[k] * w0 + q[k] * w1);
+                    }
+                }
             }
             const double sa = wave_sum_d((a[0] + a[1]) + (a[2] + a[3]));
             const double sbv = wave_sum_d((b[0] + b[1]) + (b[2] + b[3]));
@@ -165,6 +177,7 @@ __global__ __launch_bounds__(SYM_NW * 64) void k_nearsym(RowPanelDev d, int chun
 
 // One wave per leaf u: y_u += sum of the column sums of the blocks (t, u),
 // t != u, plus the corrections of u's rows (CSR over cluster-ordered rows).
+// Both lists go in batches of 8 loads (the last batch clamped and weighted 0).
 __global__ __launch_bounds__(64) void k_symreduce(ColPanelDev red, const double *__restrict__ colsum,
                                                   const int64_t *__restrict__ cptr,
                                                   const int32_t *__restrict__ cidx,
@@ -175,16 +188,28 @@ __global__ __launch_bounds__(64) void k_symreduce(ColPanelDev red, const double 
     const int ob = red.out_begin[u], ol = red.out_len[u];
     const int b0 = red.blk_ptr[u], b1 = red.blk_ptr[u + 1];
     for (int j = threadIdx.x; j < ol; j += 64) {
-        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int b = b0;
-        for (; b + 7 < b1; b += 8) {
+        double acc = 0;
+        for (int b = b0; b < b1; b += 8) {
+            double a[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] += colsum[red.b_val_off[b + q] + j];
+            for (int q = 0; q < 8; ++q) {
+                const double v = colsum[red.b_val_off[min(b + q, b1 - 1)] + j];
+                a[q] = (b + q < b1) ? v : 0.0;
+            }
+            acc += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
-        for (; b < b1; ++b) a[0] += colsum[red.b_val_off[b] + j];
-        double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         const int row = ob + j;
-        for (int64_t e = cptr[row]; e < cptr[row + 1]; ++e) acc += cval[e] * x[cidx[e]];
+        const int64_t e0 = cptr[row], e1 = cptr[row + 1];
+        for (int64_t e = e0; e < e1; e += 8) {
+            double a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t ee = min(e + q, e1 - 1);
+                const double v = cval[ee] * x[cidx[ee]];
+                a[q] = (e + q < e1) ? v : 0.0;
+            }
+            acc += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
         y[row] += acc;
     }
 }
