@@ -680,7 +680,9 @@ __device__ inline int find_segment(const int32_t *c0, int n, int col)
 // issuing up to 8 independent loads (segment found by binary search), then
 // every wave takes RW rows at a time and streams them with coalesced
 // non-temporal loads (4 column blocks of 64 per row, 4*RW loads in flight per
-// lane); rows past the end repeat the last row, whose sums are dropped.
+// lane; the last < 4 blocks of a row are issued together under per-lane
+// predicates); rows past the end repeat the last row, whose sums are dropped
+// (cheaper than branching around them).
 // Per-row partial sums live in LDS across chunks.
 template <typename VT, typename XT, typename YT, int ROLE, int NW, int RW>
 __global__ __launch_bounds__(NW * 64) void k_rowpanel(RowPanelDev d, int g0, int chunk,
@@ -749,10 +751,18 @@ __global__ __launch_bounds__(NW * 64) void k_rowpanel(RowPanelDev d, int g0, int
 #pragma unroll
                     for (int k = 0; k < 4; ++k) acc[i][k] += (A)stream_load(rows[i] + c + 64 * k) * xv[k];
             }
-            for (; c < clen; c += 64) {
-                const A xv = xs[c];
+            if (c < clen) {  // fewer than 4 column blocks left: issue them together
+                A xv[3];
 #pragma unroll
-                for (int i = 0; i < RW; ++i) acc[i][0] += (A)stream_load(rows[i] + c) * xv;
+                for (int k = 0; k < 3; ++k) xv[k] = (c + 64 * k < clen) ? xs[c + 64 * k] : A(0);
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    VT p[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) p[k] = (c + 64 * k < clen) ? stream_load(rows[i] + c + 64 * k) : VT(0);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) acc[i][k] += (A)p[k] * xv[k];
+                }
             }
 #pragma unroll
             for (int i = 0; i < RW; ++i) {
