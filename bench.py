@@ -143,6 +143,89 @@ def cpu_baseline(verts, tris, q, sample, xin):
     return dict(y=y, t=t, threads=threads)
 
 
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def batching(torch, h2b, synth, reps):
+    """Many right-hand sides and many meshes (FP32 far field, FP64 nearfield):
+    64 N(0,1) right-hand sides on the 32,768-triangle sphere (order 4
+    recompressed to 1e-6, leaf 32, q_near 4) with the autotuned matrix-core
+    coupling, and 16 spheres / ellipsoids of 2,048 to 32,768 triangles (semi-
+    axes U[0.5, 2]) captured into one graph."""
+    dev = torch.device("cuda:0")
+    res = {}
+    v, t = synth.octa_sphere(64)
+    for name, kern in (("G", "slp"), ("K", "dlp")):
+        op = h2b.Operator(v, t, kernel=kern, leaf=32, order_m=4, q_near=4, recompress_tol=1e-6,
+                          farfield_dtype="f32")
+        ref = h2b.Operator(v, t, kernel=kern, leaf=32, order_m=4, q_near=4, recompress_tol=1e-6)
+        inf = op.info()
+        tune_us = op.tune(64)
+        X = torch.tensor(synth.random_vector(op.shape[1], 601, cols=64), device=dev).t().contiguous().t()
+        Y = torch.zeros((op.shape[0], 64), dtype=torch.float64, device=dev).t().contiguous().t()
+        op.matvec(X, Y)
+        torch.cuda.synchronize()
+        # accuracy of two columns against the FP64 single-vector products
+        Y.zero_()
+        op.matvec(X, Y)
+        errs = []
+        for c in (0, 63):
+            y1 = torch.zeros(op.shape[0], dtype=torch.float64, device=dev)
+            ref.matvec(X[:, c].contiguous(), y1)
+            errs.append(float(torch.linalg.norm(Y[:, c] - y1) / torch.linalg.norm(y1)))
+        op.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.matvec(X, Y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        ph = op.phase_times()
+        op.set_timing(False)
+        flops = 2.0 * inf["coupling_entries"] * 64
+        tf = flops / ph["coupling"] / 1e9
+        res[name + "_64rhs"] = {
+            "ms": round(ms, 4), "rhs_per_s": round(64 / ms * 1e3, 1), "phases_ms": ph,
+            "coupling_tflops": round(tf, 2), "coupling_mfma_frac": round(tf / MFMA_F32_PEAK_TFLOPS, 4),
+            "coupling_flops": flops, "tune_us": round(tune_us, 2), "rel_err_vs_fp64": errs,
+        }
+        log("%s x 64 rhs: %.3f ms (coupling %.3f ms, %.1f TFLOP/s on matrix cores)" % (name, ms, ph["coupling"], tf))
+        del op, ref
+    rng = np.random.default_rng(602)
+    ops, items, ntri = [], [], 0
+    for k in range(16):
+        s = int(rng.integers(16, 65))
+        a, b, c = rng.uniform(0.5, 2.0, size=3)
+        if k % 2 == 0:
+            a = b = c
+        vv, tt = synth.ellipsoid(s, a, b, c)
+        kern = "slp" if k % 3 else "dlp"
+        op = h2b.Operator(vv, tt, kernel=kern, leaf=32, order_m=4, q_near=4, recompress_tol=1e-6,
+                          farfield_dtype="f32")
+        x = torch.tensor(synth.random_vector(op.shape[1], 610 + k), device=dev)
+        y = torch.zeros(op.shape[0], dtype=torch.float64, device=dev)
+        ops.append(op)
+        items.append((op, x, y))
+        ntri += len(tt)
+    batch = h2b.Batch(items)
+    batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.launch()
+    torch.cuda.synchronize()
+    bms = (time.perf_counter() - t0) * 1e3 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for op, x, y in items:
+            op.matvec(x, y)
+    torch.cuda.synchronize()
+    ems = (time.perf_counter() - t0) * 1e3 / reps
+    res["batch16"] = {"meshes": 16, "triangles": ntri, "graph_launch_ms": round(bms, 4),
+                      "eager_sequence_ms": round(ems, 4)}
+    log("batch of 16 meshes (%d triangles): one graph launch %.3f ms, eager sequence %.3f ms" % (ntri, bms, ems))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +239,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 2 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -324,6 +408,9 @@ def main():
                         "rel_diff": {p: detail[o + "32"]["rel_diff_vs_fp64" + ("_T" if tr else "")]
                                      for p, o, tr in PRODUCTS},
                         "step_gbps": round(step_bytes["32"] / ms32 / 1e6, 1)}
+
+    if not args.no_batching:
+        out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))
 
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float64, device=dev)

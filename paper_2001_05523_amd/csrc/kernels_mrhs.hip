@@ -24,15 +24,45 @@ template <> struct AccM<float> { using type = float; };
 template <> struct AccM<bf16_t> { using type = float; };
 
 
-// Input row of panel column c: walks the group's segments (small count).
-__device__ inline int seg_row(const RowPanelDev &d, int s0, int s1, int c)
-{
-    int s = s0;
-    while (s + 1 < s1 && c >= d.seg_len[s]) {
-        c -= d.seg_len[s];
-        ++s;
+// Segment descriptors of a group (column offset and input row of every
+// segment), held in LDS for groups of up to MSEG segments and read from
+// global memory otherwise.
+constexpr int MSEG = 128;
+struct SegMap {
+    const int32_t *c0, *in;
+    int n;
+    // input row of panel column c: binary search for the last segment with
+    // c0 <= c (a zero-length segment shares its start with the next one)
+    __device__ int row(int c) const
+    {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (c0[mid] <= c)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return in[lo] + (c - c0[lo]);
     }
-    return d.seg_in[s] + c;
+};
+
+// Loads the descriptors of group g into the LDS arrays (all threads of the
+// block call it; it ends with a barrier).
+__device__ inline SegMap load_segments(const RowPanelDev &d, int g, int32_t *lc0, int32_t *lin)
+{
+    const int s0 = d.seg_ptr[g], n = d.seg_ptr[g + 1] - s0;
+    SegMap m{d.seg_c0 + s0, d.seg_in + s0, n};
+    if (n <= MSEG) {
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            lc0[e] = m.c0[e];
+            lin[e] = m.in[e];
+        }
+        m.c0 = lc0;
+        m.in = lin;
+    }
+    __syncthreads();
+    return m;
 }
 
 // Thread (t) owns rows 4*(t/16) .. +3 (64 rows per pass) and RB/16 right-hand
@@ -47,10 +77,11 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs(RowPanelDev d, int g0, con
     constexpr int CR = RB / 16;
     __shared__ A Ps[64][KC + 1];
     __shared__ A Xs[KC][RB];
+    __shared__ int32_t lc0[MSEG], lin[MSEG];
     const int g = g0 + blockIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
     const int64_t off = d.val_off[g];
-    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const SegMap segs = load_segments(d, g, lc0, lin);
     const int t = threadIdx.x;
     const int rq = (t / 16) * 4, cq = (t % 16) * CR;
     for (int r0 = 0; r0 < nr; r0 += 64) {
@@ -61,13 +92,15 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs(RowPanelDev d, int g0, con
             for (int j = 0; j < CR; ++j) acc[i][j] = 0;
         for (int c0 = 0; c0 < nc; c0 += KC) {
             const int cl = min(KC, nc - c0);
+#pragma unroll
             for (int e = t; e < 64 * KC; e += NT) {
                 const int i = e / KC, k = e % KC;
                 Ps[i][k] = (r0 + i < nr && k < cl) ? (A)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : A(0);
             }
+#pragma unroll
             for (int e = t; e < KC * RB; e += NT) {
                 const int k = e / RB, r = e % RB;
-                Xs[k][r] = (k < cl) ? (A)x[(int64_t)seg_row(d, s0, s1, c0 + k) * RB + r] : A(0);
+                Xs[k][r] = (k < cl) ? (A)x[(int64_t)segs.row(c0 + k) * RB + r] : A(0);
             }
             __syncthreads();
 #pragma unroll 8
@@ -119,10 +152,11 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0
     using S = typename std::conditional<BF, bf16_t, float>::type;
     __shared__ S As[64][KC + (BF ? 8 : 1)];
     __shared__ S Bs[KC][RB + (BF ? 8 : 1)];
+    __shared__ int32_t lc0[MSEG], lin[MSEG];
     const int g = g0 + blockIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
     const int64_t off = d.val_off[g];
-    const int s0 = d.seg_ptr[g], s1 = d.seg_ptr[g + 1];
+    const SegMap segs = load_segments(d, g, lc0, lin);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int li = lane % 16, lk = lane / 16;
     for (int r0 = 0; r0 < nr; r0 += 64) {
@@ -131,13 +165,15 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0
         for (int q = 0; q < TPW; ++q) acc[q] = mf4{0.f, 0.f, 0.f, 0.f};
         for (int c0 = 0; c0 < nc; c0 += KC) {
             const int cl = min(KC, nc - c0);
+#pragma unroll
             for (int e = t; e < 64 * KC; e += NT) {
                 const int i = e / KC, k = e % KC;
                 As[i][k] = (r0 + i < nr && k < cl) ? (S)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : (S)0.f;
             }
+#pragma unroll
             for (int e = t; e < KC * RB; e += NT) {
                 const int k = e / RB, r = e % RB;
-                Bs[k][r] = (k < cl) ? (S)x[(int64_t)seg_row(d, s0, s1, c0 + k) * RB + r] : (S)0.f;
+                Bs[k][r] = (k < cl) ? (S)x[(int64_t)segs.row(c0 + k) * RB + r] : (S)0.f;
             }
             __syncthreads();
 #pragma unroll
@@ -211,11 +247,13 @@ __global__ __launch_bounds__(NT) void k_colpanel_mrhs(ColPanelDev d, int g0, con
             const XT *xin = x + (int64_t)d.b_in[b] * RB;
             for (int i0 = 0; i0 < nrb; i0 += KC) {
                 const int il = min(KC, nrb - i0);
+#pragma unroll
                 for (int e = t; e < KC * 64; e += NT) {
                     const int i = e / 64, j = e % 64;
                     Ps[i][j] = (i < il && j0 + j < ol) ? (A)base[(int64_t)(i0 + i) * stride + j] : A(0);
                 }
-                for (int e = t; e < KC * RB; e += NT) {
+    #pragma unroll
+            for (int e = t; e < KC * RB; e += NT) {
                     const int i = e / RB, r = e % RB;
                     Xs[i][r] = (i < il) ? (A)xin[(int64_t)(i0 + i) * RB + r] : A(0);
                 }
