@@ -134,7 +134,9 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs(RowPanelDev d, int g0, con
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 mb8 __attribute__((ext_vector_type(8)));
 
-// Matrix-core version.  Wave w computes the 16x16 output tiles (row tile,
+// Matrix-core version.  The next chunk of panel columns and input rows is
+// fetched into registers while the current one is multiplied from LDS.
+// Wave w computes the 16x16 output tiles (row tile,
 // rhs tile) with index w, w+4, ... among the 4 x (RB/16) tiles of a 64-row
 // pass.  FP32: v_mfma_f32_16x16x4f32, lane l holds A[l%16][l/16] and
 // B[l/16][l%16].  BF16: v_mfma_f32_16x16x32_bf16, lane l holds
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0
     static_assert(KC % KS == 0, "chunk must be a multiple of the instruction depth");
     constexpr int TILES = 4 * (RB / 16);
     constexpr int TPW = (TILES + 3) / 4;
+    constexpr int EA = 64 * KC / NT, EB = KC * RB / NT;  // staged elements per thread
     using S = typename std::conditional<BF, bf16_t, float>::type;
     __shared__ S As[64][KC + (BF ? 8 : 1)];
     __shared__ S Bs[KC][RB + (BF ? 8 : 1)];
@@ -160,28 +163,46 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int li = lane % 16, lk = lane / 16;
     for (int r0 = 0; r0 < nr; r0 += 64) {
+        const int rt = min(64, nr - r0);  // rows of this pass
+        // next chunk's panel and input entries, fetched into registers while
+        // the current chunk is multiplied
+        S ra[EA], rb[EB];
+        auto fetch = [&](int c0) {
+            const int cl = min(KC, nc - c0);
+#pragma unroll
+            for (int q = 0; q < EA; ++q) {
+                const int e = t + q * NT, i = e / KC, k = e % KC;
+                ra[q] = (i < rt && k < cl) ? (S)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : (S)0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < EB; ++q) {
+                const int e = t + q * NT, k = e / RB, r = e % RB;
+                rb[q] = (k < cl) ? (S)x[(int64_t)segs.row(c0 + k) * RB + r] : (S)0.f;
+            }
+        };
         mf4 acc[TPW];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) acc[q] = mf4{0.f, 0.f, 0.f, 0.f};
+        fetch(0);
         for (int c0 = 0; c0 < nc; c0 += KC) {
-            const int cl = min(KC, nc - c0);
 #pragma unroll
-            for (int e = t; e < 64 * KC; e += NT) {
-                const int i = e / KC, k = e % KC;
-                As[i][k] = (r0 + i < nr && k < cl) ? (S)vals[off + (int64_t)(r0 + i) * nc + c0 + k] : (S)0.f;
+            for (int q = 0; q < EA; ++q) {
+                const int e = t + q * NT;
+                As[e / KC][e % KC] = ra[q];
             }
 #pragma unroll
-            for (int e = t; e < KC * RB; e += NT) {
-                const int k = e / RB, r = e % RB;
-                Bs[k][r] = (k < cl) ? (S)x[(int64_t)segs.row(c0 + k) * RB + r] : (S)0.f;
+            for (int q = 0; q < EB; ++q) {
+                const int e = t + q * NT;
+                Bs[e / RB][e % RB] = rb[q];
             }
             __syncthreads();
+            if (c0 + KC < nc) fetch(c0 + KC);
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 const int tile = wave + 4 * q;
                 if (tile >= TILES) break;
                 const int ti = (tile % 4) * 16, tj = (tile / 4) * 16;
-                if (r0 + ti >= nr) continue;
+                if (ti >= rt) continue;
 #pragma unroll
                 for (int k0 = 0; k0 < KC; k0 += KS) {
                     if constexpr (BF) {
