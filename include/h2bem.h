@@ -144,11 +144,12 @@ typedef struct {
     int transposed_copy;    /* 1: also store the nearfield and coupling matrices transposed and
                                grouped by column cluster, so that A^T x streams rows like A x
                                (twice that storage); 0: A^T x reads the one copy by columns */
-    int symmetric_near;     /* 1: for G on one cluster tree (rows == cols) also store every pair of
-                               nearfield leaves once (N_tt and N_ts, s > t) plus the sparse
-                               difference G_ji - G_ij of the touching pairs across leaves; the
-                               single-vector products G x and G^T x then read about half the
-                               nearfield bytes (0.53x the nearfield storage extra) */
+    int symmetric_near;     /* 1: for G on one cluster tree (rows == cols) with leaves of at most 64
+                               triangles, also store every pair of nearfield leaves once (N_tt and
+                               N_ts, s > t) plus the sparse difference G_ji - G_ij of the touching
+                               pairs across leaves; the single-vector products G x and G^T x then
+                               read about half the nearfield bytes (0.53x the nearfield storage
+                               extra).  Ignored otherwise. */
 } h2b_params;
 
 /* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64,

@@ -335,7 +335,10 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
     if (p.transposed_copy) make_transposed_copies(*op, st);
-    if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols) make_symmetric_near(*op, st);
+    // the once-per-pair kernel keeps a leaf's rows in LDS: leaves of at most 64
+    if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols && op->near.max_nrows <= 64 &&
+        op->near.ngroups() > 0)
+        make_symmetric_near(*op, st);
 
     // work vectors
     const size_t wsz = basis_size(p.farfield_dtype);

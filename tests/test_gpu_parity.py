@@ -113,6 +113,78 @@ def test_h2_parity_against_oracle_h2(kernel, s, leaf, m):
         assert err_oracle < 1e-2
 
 
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_degenerate_meshes_against_dense_oracle(kernel):
+    """Degenerate inputs against the oracle's H^2 matrix (the dense matrix
+    when there is no far field) to rounding: one pair of triangles in each
+    relation (one cluster), the octahedron with a leaf larger than the mesh,
+    and a leaf of one triangle (deepest tree, far field down to single
+    triangles).  Nothing may fail on them."""
+    h = _lib()
+    cases = [synth.single_pair(k) for k in ("edge", "vertex", "disjoint")]
+    cases += [synth.octa_sphere(1), synth.octa_sphere(2)]
+    for i, (v, t) in enumerate(cases):
+        A = (oracle.slp_dense if kernel == "slp" else oracle.dlp_dense)(v, t, 4)
+        for leaf in ((100,) if i < 4 else (1, 100)):
+            op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=2, q_near=4)
+            H, _ = h2.h2_dense(v, t, kernel, leaf, 2, near_matrix=A)
+            if leaf == 100:
+                assert op.info()["nfar"] == 0 and np.array_equal(H, A)
+            for trans in (False, True):
+                x = synth.random_vector(A.shape[0] if trans else A.shape[1], 341 + i)
+                y = _run(op, x, trans=trans)
+                ref = (H.T if trans else H) @ x
+                scale = max(np.max(np.abs(ref)), 1e-300)
+                assert np.max(np.abs(y - ref)) <= 1e-10 * scale + 1e-14, (i, leaf, trans)
+
+
+def test_double_layer_vanishes_on_flat_plate():
+    """On a plane <x - y, n_y> = 0, so every entry of K vanishes (the oracle's
+    dense K is exactly zero) and so must the nearfield product, to rounding.
+    The far field is the normal derivative of the interpolant; across a flat
+    cluster the Chebyshev points in the normal direction collapse onto a
+    widened degenerate box side, so it is only small (interpolation error
+    amplified by that degenerate width), not zero."""
+    h = _lib()
+    v, t = synth.flat_plate(8)
+    g = h.Operator(v, t, kernel="slp", leaf=16, order_m=3, q_near=4, far_disabled=True)
+    near = h.Operator(v, t, kernel="dlp", leaf=16, order_m=3, q_near=4, far_disabled=True)
+    full = h.Operator(v, t, kernel="dlp", leaf=16, order_m=3, q_near=4)
+    assert full.info()["nfar"] > 0
+    assert np.max(np.abs(oracle.dlp_dense(v, t, 4))) == 0.0
+    x = synth.random_vector(near.shape[1], 351)
+    yg = _run(g, synth.random_vector(g.shape[1], 352))
+    assert np.max(np.abs(_run(near, x))) <= 1e-12 * np.max(np.abs(yg))
+    assert np.max(np.abs(_run(full, x))) <= 1e-3 * np.max(np.abs(yg))
+
+
+def test_largest_order_and_quadrature():
+    """Order 6 (k = 216 coefficients per cluster, panels wider than a wave)
+    and q_near 16, the largest the library accepts, against the oracle's H^2."""
+    h = _lib()
+    v, t = synth.octa_sphere(4)
+    A = oracle.slp_dense(v, t, 16)
+    op = h.Operator(v, t, kernel="slp", leaf=8, order_m=6, q_near=16)
+    assert op.info()["nfar"] > 0 and op.info()["max_rank_row"] == 216
+    H, _ = h2.h2_dense(v, t, "slp", 8, 6, near_matrix=A)
+    for trans in (False, True):
+        x = synth.random_vector(A.shape[0], 361 + trans)
+        assert _maxrel(_run(op, x, trans=trans), (H.T if trans else H) @ x) <= 1e-11
+
+
+def test_leaves_larger_than_64_keep_the_full_nearfield():
+    """The once-per-pair nearfield needs leaves of at most 64; with larger
+    leaves G is assembled without it and stays exact."""
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    op = h.Operator(v, t, kernel="slp", leaf=200, order_m=2, q_near=4)
+    assert op.info()["near_sym_entries"] == 0
+    A = _dense(8, "slp", 4)
+    H, _ = h2.h2_dense(v, t, "slp", 200, 2, near_matrix=A)
+    x = synth.random_vector(A.shape[1], 371)
+    assert _maxrel(_run(op, x), H @ x) <= 1e-11
+
+
 @pytest.mark.parametrize("kernel,s,leaf", [("slp", 16, 16), ("dlp", 16, 16), ("slp", 16, 32)])
 def test_recompressed_against_oracle_h2(kernel, s, leaf):
     """Algebraic recompression of the order-4 interpolation bases to 1e-6
