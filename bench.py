@@ -351,6 +351,19 @@ def main():
                 np.linalg.norm(a - r) / np.linalg.norm(r))
     traffic_config = {"s": args.s, "leaf": args.leaf, "order": args.order, "q_near": args.q_near,
                       "tol": args.tol}
+    # measured read ceiling of this GPU: torch's sum over 8 GiB of doubles
+    buf = torch.ones(1 << 30, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        buf.sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        buf.sum()
+    torch.cuda.synchronize()
+    read_gbps = 8 * (1 << 30) * 5 / (time.perf_counter() - t0) / 1e9
+    del buf
+    torch.cuda.empty_cache()
+    log("read ceiling (torch sum over 8 GiB): %.0f GB/s" % read_gbps)
     # the same kernel with every phase on one stream (no overlap with the far field)
     dop = ops[dominant[0]]
     dop.set_overlap(False)
@@ -400,6 +413,8 @@ def main():
                      "frac": round(dominant[3] / solo_k / 1e6 / HBM_PEAK_GBS, 4),
                      "note": "same launches with every phase on one stream (h2b_op_set_overlap 0), "
                              "timed after the step"},
+            "measured_read_gbps": round(read_gbps, 1),
+            "solo_frac_of_measured_read": round(dominant[3] / solo_k / 1e6 / read_gbps, 4),
         },
         "detail": detail,
     }

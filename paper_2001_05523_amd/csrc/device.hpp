@@ -93,6 +93,11 @@ void launch_rowpanel_mrhs(const RowPanels &rp, int g0, int g1, int rb, const VT 
 template <typename VT>
 void launch_rowpanel_mrhs_mfma(const RowPanels &rp, int g0, int g1, int rb, int kc, const VT *vals,
                                const float *x, float *y, bool accumulate, hipStream_t st);
+// Y (+)= P X for every group (at most 64 rows) on matrix cores, FP32 or FP64,
+// columns split over the four waves of a group, operands read directly.
+template <typename T>
+void launch_panel_mfma(const RowPanels &rp, int g0, int g1, int rb, const T *vals, const T *x, T *y,
+                       bool accumulate, hipStream_t st);
 template <typename VT, typename XT, typename YT>
 void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
                           bool accumulate, hipStream_t st, Role role);

@@ -238,6 +238,137 @@ __global__ __launch_bounds__(NT) void k_rowpanel_mrhs_mfma(RowPanelDev d, int g0
     }
 }
 
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+// 16x16x4 matrix instructions: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// (both types) and receives D[row(l/16, j)][l%16], j < 4: rows 4(l/16)+j for
+// FP32 and (l/16)+4j for FP64 (checked on the device with an in-bounds probe).
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> {
+    using type = mf4;
+    __device__ static type mma(float a, float b, type c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int j) { return 4 * q + j; }
+};
+template <> struct MfmaAcc<double> {
+    using type = md4;
+    __device__ static type mma(double a, double b, type c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int q, int j) { return q + 4 * j; }
+};
+
+constexpr int SK_CHUNK = 2048;  // panel columns whose input rows are looked up per pass
+
+// Y[rows of g] (+)= P_g X[columns of g] on matrix cores (16x16x4, FP32 or
+// FP64), for groups of at most 64 rows.  The four waves split the columns
+// (16 at a time, wave w taking blocks w, w+4, ...) and read both operands
+// straight from memory: within a block, lane (i, q) = (l % 16, l / 16) takes
+// columns 4q .. 4q+3 in four steps, for the panel entry of row i and for the
+// input row of those columns at right-hand side i, so every step is one
+// matrix instruction per 16x16 output tile with no staging through LDS.  The
+// input row of every column is looked up once per group (binary search over
+// the segment descriptors) into LDS.  The four partial tiles are summed in
+// LDS at the end, in a fixed order.
+template <typename T, int RB>
+__global__ __launch_bounds__(NT) void k_panel_mfma(RowPanelDev d, int g0, const T *__restrict__ vals,
+                                                   const T *__restrict__ x, T *__restrict__ y, int accumulate)
+{
+    using M = MfmaAcc<T>;
+    using V = typename M::type;
+    constexpr int CT = RB / 16;
+    __shared__ int32_t lc0[MSEG], lin[MSEG];
+    __shared__ int32_t rowidx[SK_CHUNK];
+    __shared__ T red[2][4][CT][4][64];  // two waves' partial tiles
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    if (nr == 0) return;  // uniform over the block
+    const int64_t off = d.val_off[g];
+    const SegMap segs = load_segments(d, g, lc0, lin);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane % 16, lq = lane / 16;
+    const int nrt = (nr + 15) / 16;  // row tiles (<= 4)
+    V acc[4][CT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) acc[a][b] = V{0, 0, 0, 0};
+    for (int c0 = 0; c0 < nc; c0 += SK_CHUNK) {
+        const int cl = min(SK_CHUNK, nc - c0);
+        for (int c = t; c < cl; c += NT) rowidx[c] = segs.row(c0 + c);
+        __syncthreads();
+        for (int kb = 16 * wave; kb < cl; kb += 64) {
+            T av[4][4], bv[CT][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kb + 4 * lq + j;
+                const bool kin = k < cl;
+                const int kc = kin ? k : cl - 1;
+                const T *xr = x + (int64_t)rowidx[kc] * RB + li;
+#pragma unroll
+                for (int b = 0; b < CT; ++b) bv[b][j] = kin ? xr[16 * b] : T(0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int r = min(16 * a + li, nr - 1);
+                    av[a][j] = (a < nrt && kin) ? vals[off + (int64_t)r * nc + c0 + kc] : T(0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    if (a >= nrt) continue;
+#pragma unroll
+                    for (int b = 0; b < CT; ++b) acc[a][b] = M::mma(av[a][j], bv[b][j], acc[a][b]);
+                }
+        }
+        __syncthreads();
+    }
+    // partial tiles: waves 2, 3 -> LDS, waves 0, 1 add; wave 1 -> LDS, wave 0 adds
+    if (wave >= 2)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[wave - 2][a][b][j][lane] = acc[a][b][j];
+    __syncthreads();
+    if (wave < 2)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[a][b][j] += red[wave][a][b][j][lane];
+    __syncthreads();
+    if (wave == 1)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[0][a][b][j][lane] = acc[a][b][j];
+    __syncthreads();
+    if (wave == 0) {
+        const int ob = d.out_begin[g];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            if (a >= nrt) continue;
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * a + M::row(lq, j);
+                    if (row >= nr) continue;
+                    const T v = acc[a][b][j] + red[0][a][b][j][lane];
+                    T *dst = y + (int64_t)(ob + row) * RB + 16 * b + li;
+                    *dst = accumulate ? *dst + v : v;
+                }
+        }
+    }
+}
+
 // Transposed product: Y[ob + j][:] (+)= sum_b sum_i P_b[i][c0 + j] X[in_b + i][:],
 // 64 outputs rows per pass, rows of the blocks in chunks of KC staged in LDS.
 template <typename VT, typename XT, typename YT, int ROLE, int RB>
@@ -391,6 +522,23 @@ void launch_rowpanel_mrhs_mfma(const RowPanels &rp, int g0, int g1, int rb, int 
     hip_check(hipGetLastError(), "row panel (matrix core) launch");
 }
 
+template <typename T>
+void launch_panel_mfma(const RowPanels &rp, int g0, int g1, int rb, const T *vals, const T *x, T *y,
+                       bool accumulate, hipStream_t st)
+{
+    check_rb(rb);
+    if (rp.max_nrows > 64) fail(H2B_EINVAL, "matrix-core panel product needs groups of at most 64 rows");
+    if (g1 <= g0) return;
+    const int acc = accumulate ? 1 : 0;
+    if (rb == 16)
+        hipLaunchKernelGGL((k_panel_mfma<T, 16>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+    else if (rb == 32)
+        hipLaunchKernelGGL((k_panel_mfma<T, 32>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+    else
+        hipLaunchKernelGGL((k_panel_mfma<T, 64>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+    hip_check(hipGetLastError(), "panel (matrix core, split columns) launch");
+}
+
 template <typename VT, typename XT, typename YT>
 void launch_colpanel_mrhs(const ColPanels &cp, int g0, int g1, int rb, const VT *vals, const XT *x, YT *y,
                           bool accumulate, hipStream_t st, Role role)
@@ -446,6 +594,10 @@ H2B_MRHS_INST(float, float, float)
 H2B_MRHS_INST(float, float, double)
 H2B_MRHS_INST(bf16_t, float, float)
 #undef H2B_MRHS_INST
+template void launch_panel_mfma<float>(const RowPanels &, int, int, int, const float *, const float *, float *,
+                                       bool, hipStream_t);
+template void launch_panel_mfma<double>(const RowPanels &, int, int, int, const double *, const double *,
+                                        double *, bool, hipStream_t);
 template void launch_rowpanel_mrhs_mfma<float>(const RowPanels &, int, int, int, int, const float *, const float *,
                                                float *, bool, hipStream_t);
 template void launch_rowpanel_mrhs_mfma<bf16_t>(const RowPanels &, int, int, int, int, const bf16_t *,

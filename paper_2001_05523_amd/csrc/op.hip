@@ -541,6 +541,13 @@ static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *
     }
     const RowPanels &P = trans ? op.cpl_R : op.cpl;
     const C *vals = trans ? op.cpl_R_vals.as<C>() : op.cpl_vals.as<C>();
+    if constexpr (std::is_same<F, C>::value) {
+        // FP32 or FP64: matrix cores, columns split over the waves
+        if (P.max_nrows <= 64) {
+            launch_panel_mfma<F>(P, 0, P.ngroups(), rb, vals, xhat, yhat, true, st);
+            return;
+        }
+    }
     if constexpr (std::is_same<F, float>::value)
         launch_rowpanel_mrhs_mfma<C>(P, 0, P.ngroups(), rb, kc, vals, xhat, yhat, true, st);
     else
@@ -571,7 +578,11 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
     auto nearfield = [&] {
         launch_fill_zero<double>(ypn, nout * rb, ns);
         mark(5, ns);
-        if (!trans)
+        const RowPanels &NP = trans ? op.near_R : op.near;
+        const double *nv = trans ? op.near_R_vals.as<double>() : op.near_vals.as<double>();
+        if ((!trans || op.has_R) && NP.max_nrows <= 64)
+            launch_panel_mfma<double>(NP, 0, NP.ngroups(), rb, nv, xp, ypn, true, ns);
+        else if (!trans)
             launch_rowpanel_mrhs<double, double, double>(op.near, 0, op.near.ngroups(), rb,
                                                          op.near_vals.as<double>(), xp, ypn, true, ns, Role::Near);
         else if (op.has_R)
