@@ -48,7 +48,7 @@ typedef enum {
     H2B_ENOMEM = -2,   /* host or device allocation failed */
     H2B_EDEVICE = -3,  /* a HIP call failed */
     H2B_ESTATE = -4,   /* handle in the wrong state for this call */
-    H2B_ENOTSUP = -5   /* valid request this build does not support */
+    H2B_ENOTSUP = -5   /* valid request the library does not support */
 } h2b_status;
 
 typedef enum { H2B_P0 = 0, H2B_P1 = 1 } h2b_space;        /* triangles (I) / vertices (J) */
