@@ -202,8 +202,9 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
  * y: device array of (trans ? cols : rows) x nrhs doubles, column j at y + j*ldy.
  * With nrhs > 1 the right-hand sides are processed in blocks (16, 32 or 64
  * columns, chosen by h2b_op_tune or from nrhs) as small GEMMs that read every
- * stored matrix once per block; the coupling product of the F32/BF16 far field
- * runs on matrix cores (MFMA) with FP32 accumulation.  The first call with
+ * stored matrix once per block; the nearfield and coupling blocks of groups up
+ * to 64 rows run on matrix cores (MFMA: FP64 nearfield, FP32/FP64 coupling
+ * with accumulation in its type, BF16 coupling with FP32 accumulation).  The first call with
  * nrhs > 1 allocates the block work vectors unless h2b_op_tune did.
  * Runs asynchronously on hip_stream: the nearfield runs on a stream of the
  * operator's own that is forked from hip_stream after x is read into the
@@ -236,8 +237,8 @@ h2b_status h2b_batch_destroy(h2b_batch batch);
 
 /* Autotuner for products with nrhs (2..64) right-hand sides: times the
  * coupling product of this operator for block widths of 16, 32 and 64
- * right-hand sides (and, for the F32/BF16 far field on matrix cores, two
- * staging depths), keeps the fastest for later h2b_matvec calls with nrhs > 1,
+ * right-hand sides (and, for the BF16 far field, two staging depths of panel
+ * columns), keeps the fastest for later h2b_matvec calls with nrhs > 1,
  * and allocates the block work vectors (so that later products allocate
  * nothing).  best_us (may be NULL) receives the tuned coupling time in
  * microseconds for nrhs columns.  Synchronises hip_stream.
