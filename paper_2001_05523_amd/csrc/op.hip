@@ -594,14 +594,31 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
         mark(6, ns);
     };
     if (ns != st) nearfield();
-    launch_colpanel_mrhs<F, double, F>(Bin.leaf_F, 0, Bin.leaf_F.ngroups(), rb, Bin.leafT_vals.as<F>(), xp, xhat,
-                                       false, st, Role::Leaf);
-    for (auto &s : Bin.fw_steps)
-        launch_colpanel_mrhs<F, F, F>(Bin.trans_F, s.first, s.second, rb, Bin.transT_vals.as<F>(), xhat, xhat,
-                                      false, st, Role::Transfer);
+    // forward transformation: row panels V_t^T and [E_c0^T | E_c1^T] on matrix
+    // cores where types and sizes allow, else column products over the copies
+    bool leaf_done = false;
+    if constexpr (std::is_same<F, double>::value) {
+        if (Bin.leaf.max_nrows <= 64) {
+            launch_panel_mfma<double>(Bin.leaf, 0, Bin.leaf.ngroups(), rb, Bin.leaf_vals.as<double>(), xp, xhat,
+                                      false, st);
+            leaf_done = true;
+        }
+    }
+    if (!leaf_done)
+        launch_colpanel_mrhs<F, double, F>(Bin.leaf_F, 0, Bin.leaf_F.ngroups(), rb, Bin.leafT_vals.as<F>(), xp,
+                                           xhat, false, st, Role::Leaf);
+    for (auto &s : Bin.fw_steps) {
+        if (Bin.trans.max_nrows <= 64)
+            launch_panel_mfma<F>(Bin.trans, s.first, s.second, rb, Bin.trans_vals.as<F>(), xhat, xhat, false, st);
+        else
+            launch_colpanel_mrhs<F, F, F>(Bin.trans_F, s.first, s.second, rb, Bin.transT_vals.as<F>(), xhat, xhat,
+                                          false, st, Role::Transfer);
+    }
     mark(2, st);
     coupling_block<F, C>(op, trans, rb, op.tune_kc, xhat, yhat, st);
     mark(3, st);
+    // backward transformation: column products over the panels (row panels of
+    // single children were measured slower for these small matrices)
     for (auto &s : Bout.bw_steps)
         launch_colpanel_mrhs<F, F, F>(Bout.trans_T, s.first, s.second, rb, Bout.trans_vals.as<F>(), yhat, yhat,
                                       true, st, Role::Transfer);
