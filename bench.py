@@ -424,6 +424,22 @@ def main():
                                      for p, o, tr in PRODUCTS},
                         "step_gbps": round(step_bytes["32"] / ms32 / 1e6, 1)}
 
+    # accuracy on the 1,000 oracle rows stored for this workload, if present
+    gold_path = os.path.join(ROOT, "tests", "golden", "sphere2M_oracle_rows.json")
+    if (os.path.exists(gold_path) and args.s == 512 and args.q_near == 6 and args.order == 4
+            and args.leaf == 64 and args.tol == 1e-6):
+        with open(gold_path) as fh:
+            gold = json.load(fh)
+        rows = np.asarray(gold["rows"])
+        acc1000 = {}
+        for name in ops:
+            ref = np.asarray(gold[name[0]]["y"])
+            got = y[name][rows]
+            acc1000[name] = {"rel_2norm": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                             "max_row_over_max": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
+        out["oracle_rows_1000"] = acc1000
+        log("1,000 stored oracle rows: " + ", ".join("%s %.3e" % (k, v["rel_2norm"]) for k, v in acc1000.items()))
+
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))
 
