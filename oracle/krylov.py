@@ -1,0 +1,147 @@
+"""Test infrastructure only: the Dirichlet-to-Neumann system and the conjugate
+gradient method, dense and in double precision (small meshes only).
+
+* Mixed mass matrix (Section 1): m_ij = int psi_i phi_j for the piecewise
+  constant psi_i (triangles) and the piecewise linear hat functions phi_j
+  (vertices).  On a flat triangle the hat function of one of its corners
+  integrates to a third of the area, so m_ij = |tau_i| / 3 when j is a corner
+  of tau_i and 0 otherwise.
+* Dirichlet-to-Neumann system (Section 1, eq. (matrix_dtn)): G t = (M/2 + K) u
+  for the Neumann coefficients t given the Dirichlet coefficients u.  Its
+  exact solution is the plain definition G^{-1} (M/2 + K) u, computed here by
+  a dense direct solve.
+* Conjugate gradients (Hestenes and Stiefel, 1952), the Krylov solver the
+  experiments of Section 5 run on this system with relative accuracy
+  eps_slv: stop at the first iterate whose residual satisfies
+  ||b - A x_k||_2 <= tol ||b||_2, where the residual is the one the
+  recurrence updates.
+* The test functions of Section 5: u1(x) = x1^2 - x3^2, u2 = g(., y1) and
+  u3 = g(., y2) with y1 = (1.2, 1.2, 1.2), y2 = (1.0, 0.25, 1.0), all
+  harmonic inside the unit sphere, and the L2 error of a piecewise constant
+  Neumann approximation against the exact normal derivative <grad u, n_tau>
+  on the flat triangles of the mesh.
+"""
+import math
+
+import numpy as np
+
+from . import slp_dense, dlp_dense
+from .h2 import triangle_rule
+
+FOUR_PI = 4.0 * math.pi
+Y1 = np.array([1.2, 1.2, 1.2])
+Y2 = np.array([1.0, 0.25, 1.0])
+
+
+def _areas_normals(verts, tris):
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    nrm = np.linalg.norm(cr, axis=1)
+    return 0.5 * nrm, cr / nrm[:, None]
+
+
+def mass_matrix(verts, tris):
+    """Dense mixed mass matrix M (nt x nv), m_ij = |tau_i| / 3 for the
+    corners j of tau_i."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    area, _ = _areas_normals(verts, tris)
+    M = np.zeros((len(tris), len(verts)))
+    for i in range(len(tris)):
+        for j in tris[i]:
+            M[i, j] += area[i] / 3.0
+    return M
+
+
+def cg(apply_a, b, tol, max_iter, x0=None):
+    """Conjugate gradients for a symmetric positive definite operator.
+
+    Returns (x, iterations, history) where history[k] = ||r_k|| / ||b|| for
+    the recurrence residuals r_0 .. r_iterations (the absolute norm when
+    b = 0).  Stops at the first k with ||r_k|| <= tol ||b||, or after
+    max_iter iterations, or when p^T A p is not positive (breakdown)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply_a(x) if x0 is not None else b.copy()
+    bnorm = math.sqrt(float(b @ b))
+    scale = bnorm if bnorm > 0 else 1.0
+    rho = float(r @ r)
+    history = [math.sqrt(rho) / scale]
+    p = r.copy()
+    k = 0
+    while math.sqrt(rho) > tol * bnorm and k < max_iter:
+        q = apply_a(p)
+        pq = float(p @ q)
+        if not pq > 0:
+            break
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_new = float(r @ r)
+        beta = rho_new / rho
+        rho = rho_new
+        p = r + beta * p
+        k += 1
+        history.append(math.sqrt(rho) / scale)
+    return x, k, np.array(history)
+
+
+def dtn_matrices(verts, tris, q):
+    """Dense G, K and M of one mesh (nearfield quadrature order q everywhere)."""
+    return slp_dense(verts, tris, q), dlp_dense(verts, tris, q), mass_matrix(verts, tris)
+
+
+def dtn_rhs(K, M, u):
+    """Right-hand side (M/2 + K) u of eq. (matrix_dtn)."""
+    return 0.5 * (M @ u) + K @ u
+
+
+def dtn_solve(G, K, M, u):
+    """Neumann coefficients t = G^{-1} (M/2 + K) u by a dense direct solve."""
+    return np.linalg.solve(G, dtn_rhs(K, M, u))
+
+
+# ------------------------------------------------------- test functions
+
+def u1(p):
+    return p[..., 0] ** 2 - p[..., 2] ** 2
+
+
+def grad_u1(p):
+    g = np.zeros_like(p)
+    g[..., 0] = 2.0 * p[..., 0]
+    g[..., 2] = -2.0 * p[..., 2]
+    return g
+
+
+def _point_source(y):
+    def u(p):
+        return 1.0 / (FOUR_PI * np.linalg.norm(p - y, axis=-1))
+
+    def grad(p):
+        d = p - y
+        r = np.linalg.norm(d, axis=-1)
+        return -d / (FOUR_PI * r ** 3)[..., None]
+
+    return u, grad
+
+
+u2, grad_u2 = _point_source(Y1)
+u3, grad_u3 = _point_source(Y2)
+TEST_FUNCTIONS = {"u1": (u1, grad_u1), "u2": (u2, grad_u2), "u3": (u3, grad_u3)}
+
+
+def neumann_l2_error(verts, tris, t, grad_u, q=6):
+    """|| t - <grad u, n_tau> ||_{L2(Gamma)} for the piecewise constant t,
+    integrated with the collapsed q x q Gauss rule on every triangle."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    area, n = _areas_normals(verts, tris)
+    U, W = triangle_rule(q)
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    # x(u1, u2) = a + u1 (b - a) + u2 (c - b); the rule integrates over the
+    # reference triangle of area 1/2, so the Jacobian is 2 |tau|
+    X = a[:, None, :] + U[None, :, :1] * (b - a)[:, None, :] + U[None, :, 1:2] * (c - b)[:, None, :]
+    dn = np.einsum("ikd,id->ik", grad_u(X), n)
+    err2 = np.einsum("ik,k,i->", (t[:, None] - dn) ** 2, W, 2.0 * area)
+    return math.sqrt(err2)

@@ -1,0 +1,162 @@
+"""Pins of the oracle's mass matrix, conjugate gradient method and
+Dirichlet-to-Neumann solve against facts that do not come from the oracle
+itself: exact integration of linear functions, finite termination and the
+energy-norm optimality of CG, closed-form Neumann data of harmonic functions
+and the first-order L2 convergence that Section 5 reports for the
+Dirichlet-to-Neumann problem."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov
+
+
+def _geom(v, t):
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    cr = np.cross(b - a, c - a)
+    nrm = np.linalg.norm(cr, axis=1)
+    return 0.5 * nrm, cr / nrm[:, None], (a + b + c) / 3.0
+
+
+# ---------------------------------------------------------------- mass matrix
+
+@pytest.mark.parametrize("mesh", ["sphere", "ellipsoid", "perturbed"])
+def test_mass_matrix_integrates_linear_functions_exactly(mesh):
+    """Sum_j m_ij = |tau_i| (the hat functions sum to one) and
+    Sum_j m_ij x_j = |tau_i| * centroid (a linear function equals its P1
+    interpolant, and the mean of a linear function over a triangle is its
+    value at the centroid).  Four equations for the three corner entries of a
+    row: together they fix M."""
+    if mesh == "sphere":
+        v, t = synth.octa_sphere(4)
+    elif mesh == "ellipsoid":
+        v, t = synth.ellipsoid(4, 0.7, 1.3, 2.1)
+    else:
+        v, t = synth.perturbed_sphere(4, seed=7)
+    M = krylov.mass_matrix(v, t)
+    area, _, cen = _geom(v, t)
+    assert np.allclose(M.sum(axis=1), area, rtol=1e-14, atol=0)
+    for d in range(3):
+        assert np.allclose(M @ v[:, d], area * cen[:, d], rtol=1e-12, atol=1e-15)
+    assert np.count_nonzero(M) == 3 * len(t)
+
+
+# ---------------------------------------------------------- conjugate gradients
+
+def _spd(n, eigs, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (Q * eigs) @ Q.T
+
+
+def test_cg_matches_direct_solve():
+    """On a random SPD matrix (condition 1e3) CG converges to the solution of
+    numpy's dense solver."""
+    n = 40
+    A = _spd(n, np.geomspace(1.0, 1e3, n), 1)
+    b = np.random.default_rng(2).standard_normal(n)
+    x, k, hist = krylov.cg(lambda p: A @ p, b, 1e-13, 500)
+    assert hist[-1] <= 1e-13 and k < 500
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_cg_terminates_after_as_many_steps_as_distinct_eigenvalues():
+    """In exact arithmetic CG finds the solution after at most as many steps
+    as A has distinct eigenvalues (three here, each of multiplicity ten); a
+    wrong step length or direction update loses this."""
+    A = _spd(30, np.repeat([1.0, 3.0, 10.0], 10), 3)
+    b = np.random.default_rng(4).standard_normal(30)
+    x, k, hist = krylov.cg(lambda p: A @ p, b, 1e-10, 100)
+    assert k == 3, hist
+    assert hist[2] > 1e-3
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 9])
+def test_cg_iterate_minimises_the_energy_norm_over_the_krylov_space(k):
+    """The k-th CG iterate is the minimiser of ||x* - x||_A over x0 + K_k(A, r0)
+    (the Galerkin solution on the Krylov space), computed here independently
+    from an orthonormal basis of span{r0, A r0, ..., A^{k-1} r0}."""
+    n = 25
+    A = _spd(n, np.geomspace(1.0, 50.0, n), 5)
+    rng = np.random.default_rng(6)
+    b, x0 = rng.standard_normal(n), rng.standard_normal(n)
+    x, it, hist = krylov.cg(lambda p: A @ p, b, 0.0, k, x0=x0)
+    assert it == k
+    r0 = b - A @ x0
+    kry = [r0]
+    for _ in range(k - 1):
+        kry.append(A @ kry[-1])
+    Q, _ = np.linalg.qr(np.array(kry).T)
+    y = np.linalg.solve(Q.T @ A @ Q, Q.T @ r0)
+    xg = x0 + Q @ y
+    assert np.linalg.norm(x - xg) <= 1e-9 * np.linalg.norm(xg)
+    # the recurrence residual is the true residual
+    assert abs(np.linalg.norm(b - A @ x) / np.linalg.norm(b) - hist[-1]) <= 1e-10
+
+
+def test_cg_stopping_rule_and_degenerate_cases():
+    A = _spd(20, np.geomspace(1.0, 100.0, 20), 8)
+    b = np.random.default_rng(9).standard_normal(20)
+    x, k, hist = krylov.cg(lambda p: A @ p, b, 1e-6, 100)
+    assert hist[k] <= 1e-6 < hist[k - 1]
+    assert len(hist) == k + 1 and hist[0] == pytest.approx(1.0)
+    # no iterations: the initial guess comes back
+    x0 = np.arange(20.0)
+    x, k, hist = krylov.cg(lambda p: A @ p, b, 1e-6, 0, x0=x0)
+    assert k == 0 and np.array_equal(x, x0)
+    # b = 0 from the zero guess: solved before the first step
+    x, k, hist = krylov.cg(lambda p: A @ p, np.zeros(20), 1e-6, 10)
+    assert k == 0 and not x.any()
+
+
+# ----------------------------------------------------- Dirichlet-to-Neumann
+
+def test_l2_error_of_exact_and_shifted_data():
+    """For linear u the normal derivative is the constant a . n_tau on each
+    flat triangle: the error of that P0 function is zero, and shifting it by
+    delta gives delta * sqrt(|Gamma|)."""
+    v, t = synth.octa_sphere(4)
+    area, n, _ = _geom(v, t)
+    a = np.array([0.3, -0.8, 0.5])
+    grad = lambda p: np.broadcast_to(a, p.shape)  # noqa: E731
+    assert krylov.neumann_l2_error(v, t, n @ a, grad) <= 1e-14
+    d = 0.125
+    assert krylov.neumann_l2_error(v, t, n @ a + d, grad) == pytest.approx(d * math.sqrt(area.sum()), rel=1e-12)
+
+
+def test_dtn_reproduces_linear_neumann_data():
+    """Green's formula (Section 1) holds exactly on the polyhedron for a
+    linear u, which is its own P1 interpolant and has P0 Neumann data
+    a . n_tau; the solution of eq. (matrix_dtn) differs from that only by
+    quadrature error, which falls exponentially with the order q."""
+    v, t = synth.octa_sphere(4)
+    _, n, _ = _geom(v, t)
+    a = np.array([1.0, -0.5, 0.25])
+    err = []
+    for q in (4, 8, 12):
+        G, K, M = krylov.dtn_matrices(v, t, q)
+        sol = krylov.dtn_solve(G, K, M, v @ a + 0.7)
+        err.append(np.max(np.abs(sol - n @ a)) / np.max(np.abs(n @ a)))
+    assert err[0] > 100 * err[1] > 1e4 * err[2], err
+    assert err[2] <= 1e-9, err
+
+
+def test_dtn_paper_functions_converge_first_order():
+    """Section 5: the Neumann data of u1, u2 and u3 computed from eq.
+    (matrix_dtn) converge in L2 at the rate O(h).  The observed order between
+    the two finest meshes (s = 8 and 16, h halved) is checked for each."""
+    errs = {name: [] for name in krylov.TEST_FUNCTIONS}
+    for s in (4, 8, 16):
+        v, t = synth.octa_sphere(s)
+        G, K, M = krylov.dtn_matrices(v, t, 4)
+        for name, (u, grad) in krylov.TEST_FUNCTIONS.items():
+            sol = krylov.dtn_solve(G, K, M, u(v))
+            errs[name].append(krylov.neumann_l2_error(v, t, sol, grad))
+    for name, e in errs.items():
+        assert e[0] > e[1] > e[2], (name, e)
+        rate = math.log2(e[1] / e[2])
+        assert 0.8 <= rate <= 1.6, (name, e, rate)
