@@ -293,6 +293,72 @@ h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7]);
  * Errors: H2B_EINVAL if op is NULL. */
 h2b_status h2b_op_set_overlap(h2b_op op, int enable);
 
+/* ------------------------------------------------ Dirichlet-to-Neumann solve */
+
+/* Mixed mass matrix M (Section 1): m_ij = int psi_i phi_j for the triangle
+ * indicator psi_i and the hat function phi_j of vertex j, i.e. |tau_i| / 3
+ * when j is a corner of tau_i and 0 otherwise.  trans = 0: y += alpha M x
+ * with x on the vertices (nv doubles, vertex order) and y on the triangles
+ * (nt doubles, triangle order); trans = 1: y += alpha M^T x (x on the
+ * triangles, y on the vertices).  op is any operator assembled on the mesh
+ * and supplies its device geometry (the current one after
+ * h2b_op_set_geometry).  x and y are device arrays that must not overlap.
+ * Runs asynchronously on hip_stream.  Errors: H2B_EINVAL for a NULL pointer
+ * or overlapping x and y.
+ *
+ * With the double-layer operator K this gives the right-hand side
+ * (M/2 + K) u of the Dirichlet-to-Neumann system G t = (M/2 + K) u
+ * (Section 1, eq. (matrix_dtn)) from the Dirichlet coefficients u. */
+h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, double *y,
+                           void *hip_stream);
+
+/* Conjugate gradients for A x = b with the H^2 product of a square operator
+ * (meant for the symmetric positive definite single-layer matrix G of eq.
+ * (matrix_dtn); the Krylov solver of the experiments in Section 5).
+ *
+ * Iteration (Hestenes-Stiefel): q = A p, alpha = rho / p^T q,
+ * x += alpha p, r -= alpha q, rho' = r^T r, p = r + (rho'/rho) p.  Inner
+ * products are double precision, reduced in a fixed order (the same result
+ * for the same input on the same device).  Stops at the first iterate with
+ * ||r_k||_2 <= tol ||b||_2 (r_k the updated residual; absolute when b = 0),
+ * after max_iter iterations, or on breakdown (p^T q not positive or not
+ * finite).  Every scalar of the iteration stays on the device: the host
+ * queues check_every iterations at a time (captured once into a HIP graph
+ * and replayed when use_graph = 1) and then reads the state.  The iterations
+ * queued after the stopping one change nothing (x, r and the count are
+ * frozen), so the result does not depend on check_every or use_graph.  The
+ * products of A inside the iteration run with A's precision settings (a
+ * lower-precision far field makes CG solve the perturbed system).
+ *
+ * b: device array of n doubles; x: device array of n doubles, the initial
+ * guess on entry (ignored and set to 0 when zero_guess = 1) and the last
+ * iterate on return; n = rows = columns of A.  history: NULL, or a host array
+ * of max_iter + 1 doubles receiving ||r_k|| / ||b|| for k = 0..iterations.
+ * Work vectors (3 n doubles plus small state) are allocated per call.  The
+ * call synchronises hip_stream and returns when the solve has ended.
+ * Errors: H2B_EINVAL for a non-square operator, NULL or overlapping b and x,
+ * tol < 0 or not finite, max_iter < 0, check_every < 1. */
+typedef struct {
+    double tol;        /* relative residual to reach (default 1e-8) */
+    int max_iter;      /* iteration limit (default 1000) */
+    int check_every;   /* iterations queued between two reads of the state (default 8) */
+    int use_graph;     /* 1: replay a captured HIP graph of check_every iterations (default 1) */
+    int zero_guess;    /* 1: start from x = 0 without the initial product (default 1) */
+} h2b_cg_params;
+
+typedef enum { H2B_CG_CONVERGED = 1, H2B_CG_BREAKDOWN = 2, H2B_CG_MAXITER = 3 } h2b_cg_status;
+
+typedef struct {
+    int iterations;       /* iterations done */
+    int status;           /* h2b_cg_status */
+    double rel_residual;  /* ||r_k|| / ||b|| of the last iterate */
+    double solve_ms;      /* wall time of the call, including the graph build */
+} h2b_cg_result;
+
+void h2b_cg_params_default(h2b_cg_params *p);
+h2b_status h2b_cg_solve(h2b_op A, const double *b, double *x, const h2b_cg_params *params,
+                        h2b_cg_result *result, double *history, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,20 @@ class h2b_op_stats(ctypes.Structure):
                 ("near_sym_entries", _i64), ("near_sym_columns", _i64), ("near_sym_corrections", _i64)]
 
 
+class h2b_cg_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+
+
+class h2b_cg_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+
+H2B_CG_CONVERGED, H2B_CG_BREAKDOWN, H2B_CG_MAXITER = 1, 2, 3
+CG_STATUS = {H2B_CG_CONVERGED: "converged", H2B_CG_BREAKDOWN: "breakdown", H2B_CG_MAXITER: "max_iter"}
+
+
 _SIGS = {
     "h2b_last_error": ([], ctypes.c_char_p),
     "h2b_version": ([], ctypes.c_char_p),
@@ -81,6 +95,9 @@ _SIGS = {
     "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_set_overlap": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
+    "h2b_mass_matvec": ([_vp, ctypes.c_int, _dbl, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_cg_params_default": ([_P(h2b_cg_params)], None),
+    "h2b_cg_solve": ([_vp, _vp, _vp, _P(h2b_cg_params), _P(h2b_cg_result), _vp, _vp], ctypes.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -273,10 +290,64 @@ class Operator:
         _check(h2b_op_phase_times(self.handle, _ptr(out)))
         return dict(zip(("gather", "forward", "coupling", "backward", "nearfield", "scatter", "total"), out))
 
+    def mass_matvec(self, x, y, alpha=1.0, trans=False, stream=None):
+        """y += alpha M x (x on the vertices, y on the triangles) or, with
+        trans, y += alpha M^T x, for the mixed mass matrix of the mesh."""
+        nin, nout = (self.mesh.nt, self.mesh.nv) if trans else (self.mesh.nv, self.mesh.nt)
+        _vector(x, nin, "x")
+        _vector(y, nout, "y")
+        _check(h2b_mass_matvec(self.handle, int(bool(trans)), float(alpha), _vp(x.data_ptr()),
+                               _vp(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def cg(self, b, x, tol=1e-8, max_iter=1000, check_every=8, use_graph=True, zero_guess=True,
+           history=False, stream=None):
+        """Conjugate gradients for A x = b (A square, symmetric positive
+        definite: the single-layer matrix G).  x holds the initial guess
+        (unless zero_guess) and receives the solution.  Returns a dict with
+        iterations, status, rel_residual, solve_ms and, with history, the
+        relative residual norms of iterations 0..iterations."""
+        if self.shape[0] != self.shape[1]:
+            raise ValueError("conjugate gradients need a square operator")
+        _vector(b, self.shape[0], "b")
+        _vector(x, self.shape[0], "x")
+        p = h2b_cg_params()
+        h2b_cg_params_default(ctypes.byref(p))
+        p.tol, p.max_iter, p.check_every = float(tol), int(max_iter), int(check_every)
+        p.use_graph, p.zero_guess = int(bool(use_graph)), int(bool(zero_guess))
+        r = h2b_cg_result()
+        hist = np.zeros(max(int(max_iter), 0) + 1) if history else None
+        _check(h2b_cg_solve(self.handle, _vp(b.data_ptr()), _vp(x.data_ptr()), ctypes.byref(p), ctypes.byref(r),
+                            _ptr(hist) if history else None, _stream_ptr(stream)))
+        out = dict(iterations=r.iterations, status=CG_STATUS.get(r.status, r.status),
+                   rel_residual=r.rel_residual, solve_ms=r.solve_ms)
+        if history:
+            out["history"] = hist[:r.iterations + 1]
+        return out
+
     def __del__(self, _destroy=h2b_op_destroy):
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+
+
+def _vector(v, n, name):
+    import torch
+    if not isinstance(v, torch.Tensor) or v.dtype != torch.float64 or not v.is_cuda:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if v.dim() != 1 or v.shape[0] != n or not v.is_contiguous():
+        raise ValueError("%s must be a contiguous vector of length %d" % (name, n))
+
+
+def dtn_rhs(K, u, stream=None):
+    """Right-hand side (M/2 + K) u of the Dirichlet-to-Neumann system
+    G t = (M/2 + K) u for the Dirichlet coefficients u (one per vertex) and
+    the double-layer operator K: two library calls."""
+    import torch
+    b = torch.zeros(K.mesh.nt, dtype=torch.float64, device=u.device)
+    K.mass_matvec(u, b, 0.5, stream=stream)
+    K.matvec(u, b, stream=stream)
+    return b
 
 
 class Batch:

@@ -305,4 +305,35 @@ h2b_status h2b_op_phase_times(h2b_op op, double phases_ms[7])
     });
 }
 
+void h2b_cg_params_default(h2b_cg_params *p)
+{
+    if (!p) return;
+    p->tol = 1e-8;
+    p->max_iter = 1000;
+    p->check_every = 8;
+    p->use_graph = 1;
+    p->zero_guess = 1;
+}
+
+h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, double *y, void *hip_stream)
+{
+    return guarded([&] {
+        need(op, "op");
+        h2b::mass_matvec(*op->op, trans ? 1 : 0, alpha, x, y, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_cg_solve(h2b_op A, const double *b, double *x, const h2b_cg_params *params,
+                        h2b_cg_result *result, double *history, void *hip_stream)
+{
+    return guarded([&] {
+        need(A, "A");
+        need(params, "params");
+        need(result, "result");
+        h2b_cg_result r{};
+        h2b::cg_solve(*A->op, b, x, *params, r, history, static_cast<hipStream_t>(hip_stream));
+        *result = r;
+    });
+}
+
 }  // extern "C"

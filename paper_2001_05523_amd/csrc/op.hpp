@@ -149,5 +149,10 @@ void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, 
 void slp_shape_grad(Op &op, const double *x, const double *y, double *gx, double *gy, double *gz,
                     hipStream_t st);
 void op_stats(const Op &op, h2b_op_stats &s);
+// y += alpha M x (trans = 0) or alpha M^T x (trans = 1), M the mixed mass matrix.
+void mass_matvec(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st);
+// Conjugate gradients for A x = b with the H^2 product of A.
+void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_cg_result &res, double *history,
+              hipStream_t st);
 
 }  // namespace h2b
