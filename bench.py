@@ -226,6 +226,59 @@ def batching(torch, h2b, synth, reps):
     return res
 
 
+def neumann_l2_error_u1(verts, tris, t):
+    """|| t - <grad u1, n_tau> ||_L2 for u1 = x1^2 - x3^2 on the flat triangles
+    (the normal derivative is linear on each triangle, so the three-point
+    edge-midpoint rule, exact for quadratics, integrates the square exactly)."""
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    n = cr / (2.0 * area)[:, None]
+    err2 = np.zeros(len(tris))
+    for p in (0.5 * (a + b), 0.5 * (b + c), 0.5 * (c + a)):
+        dn = 2.0 * p[:, 0] * n[:, 0] - 2.0 * p[:, 2] * n[:, 2]
+        err2 += (t - dn) ** 2 / 3.0
+    return float(np.sqrt(np.sum(err2 * area)))
+
+
+def dtn_solve(torch, h2b, ops, verts, tris, suffixes, ms_gx):
+    """Dirichlet-to-Neumann solve G t = (M/2 + K) u for u = u1 = x1^2 - x3^2 on
+    the benchmark mesh: right-hand side from the library's mass and K
+    products, conjugate gradients to 1e-8 on G (graph-replayed batches of 8
+    iterations; once more queued eagerly for comparison)."""
+    u = torch.tensor(verts[:, 0] ** 2 - verts[:, 2] ** 2, dtype=torch.float64, device="cuda")
+    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, CG tol 1e-8 from t = 0, FP64 inner products"}
+    sols = {}
+    for suffix in suffixes:
+        G, K = ops["G" + suffix], ops["K" + suffix]
+        b = h2b.dtn_rhs(K, u)
+        t = torch.zeros_like(b)
+        r = G.cg(b, t, tol=1e-8, max_iter=3000)
+        t2 = torch.zeros_like(b)
+        re = G.cg(b, t2, tol=1e-8, max_iter=3000, use_graph=False)
+        chk = b.clone()
+        G.matvec(t, chk, alpha=-1.0)
+        torch.cuda.synchronize()
+        true_rel = float(torch.linalg.norm(chk) / torch.linalg.norm(b))
+        sols[suffix] = t.cpu().numpy()
+        it = max(r["iterations"], 1)
+        d = {"iterations": r["iterations"], "status": r["status"], "rel_residual": r["rel_residual"],
+             "true_rel_residual": true_rel, "solve_ms": round(r["solve_ms"], 2),
+             "ms_per_iteration": round(r["solve_ms"] / it, 4),
+             "eager_solve_ms": round(re["solve_ms"], 2), "eager_iterations": re["iterations"],
+             "l2_error_neumann": neumann_l2_error_u1(verts, tris, sols[suffix])}
+        if ms_gx.get(suffix):
+            d["iteration_over_product"] = round(r["solve_ms"] / it / ms_gx[suffix], 3)
+        res["f64" if not suffix else "mixed"] = d
+        log("DtN solve (%s): %d iterations, %.1f ms (%.3f ms per iteration; eager %.1f ms), "
+            "residual %.2e (true %.2e), L2 error %.3e" % ("f64" if not suffix else "mixed", r["iterations"],
+                                                         r["solve_ms"], r["solve_ms"] / it, re["solve_ms"],
+                                                         r["rel_residual"], true_rel, d["l2_error_neumann"]))
+    if "32" in sols:
+        res["mixed"]["rel_diff_vs_fp64"] = float(np.linalg.norm(sols["32"] - sols[""]) / np.linalg.norm(sols[""]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +293,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
+    ap.add_argument("--no-solve", action="store_true", help="skip the Dirichlet-to-Neumann CG solve")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 2 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -439,6 +493,11 @@ def main():
                              "max_row_over_max": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
         out["oracle_rows_1000"] = acc1000
         log("1,000 stored oracle rows: " + ", ".join("%s %.3e" % (k, v["rel_2norm"]) for k, v in acc1000.items()))
+
+    if not args.no_solve:
+        out["dtn_solve"] = dtn_solve(torch, h2b, ops, verts, tris, ("", "32") if not args.no_mixed else ("",),
+                                     {"": detail["G"]["ms_Ax"],
+                                      "32": detail["G32"]["ms_Ax"] if not args.no_mixed else None})
 
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))

@@ -218,9 +218,10 @@ h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
 
 /* Batched products over several operators (e.g. meshes of different sizes):
- * captures y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  Each
- * operator runs on its own stream forked from hip_stream inside the capture,
- * so the products of different operators are concurrent branches of the graph.
+ * builds y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  The
+ * products of different operators are concurrent branches of the graph, and
+ * a single-vector product (nrhs_i = 1) is itself two branches, nearfield and
+ * far field, between the gather of x_i and the write of y_i.
  * The arrays give per-operator arguments as for h2b_matvec; the device
  * vectors are bound at creation and must stay valid while the batch exists.
  * Creation checks every argument first and allocates each operator's work
@@ -323,7 +324,8 @@ h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, 
  * ||r_k||_2 <= tol ||b||_2 (r_k the updated residual; absolute when b = 0),
  * after max_iter iterations, or on breakdown (p^T q not positive or not
  * finite).  Every scalar of the iteration stays on the device: the host
- * queues check_every iterations at a time (captured once into a HIP graph
+ * queues check_every iterations at a time (built once into a HIP graph, in
+ * which each product runs its nearfield and far field as parallel branches,
  * and replayed when use_graph = 1) and then reads the state.  The iterations
  * queued after the stopping one change nothing (x, r and the count are
  * frozen), so the result does not depend on check_every or use_graph.  The
@@ -342,7 +344,7 @@ typedef struct {
     double tol;        /* relative residual to reach (default 1e-8) */
     int max_iter;      /* iteration limit (default 1000) */
     int check_every;   /* iterations queued between two reads of the state (default 8) */
-    int use_graph;     /* 1: replay a captured HIP graph of check_every iterations (default 1) */
+    int use_graph;     /* 1: replay a HIP graph of check_every iterations (default 1) */
     int zero_guess;    /* 1: start from x = 0 without the initial product (default 1) */
 } h2b_cg_params;
 

@@ -1,8 +1,10 @@
-// Batched products over several operators (meshes of different sizes)
-// captured once into a hipGraph: every operator gets its own stream forked
-// from the caller's stream during capture, so the products of different
-// meshes are independent graph branches that run concurrently; one graph
-// launch runs the whole batch.
+// Batched products over several operators (meshes of different sizes) built
+// once into a hipGraph: the products of different meshes are independent
+// branches of the graph, and inside each single-vector product the nearfield
+// and the far field are two more parallel branches (prepare -> {nearfield,
+// far field} -> scatter).  Every piece is captured alone on one private
+// stream and added as a child-graph node, so no capture spans two streams.
+// One graph launch runs the whole batch.
 #include <hip/hip_runtime.h>
 
 #include <set>
@@ -35,31 +37,21 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
         prepare_product(*ops[i], nrhs[i]);
     }
     // the caller's stream may be the null stream, which cannot be captured:
-    // capture on a private origin stream (streams[nops]) and launch the graph
-    // on the caller's stream later
+    // capture the pieces on a private stream and launch the graph on the
+    // caller's stream later
     (void)st;
     auto b = std::make_unique<Batch>();
-    b->streams.resize(nops + 1, nullptr);
-    b->events.resize(nops + 1, nullptr);
-    for (auto &s : b->streams) hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream create");
-    for (auto &e : b->events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
-    hipStream_t origin = b->streams[nops];
-    hip_check(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal), "begin capture");
-    try {
-        hip_check(hipEventRecord(b->events[nops], origin), "fork");
-        for (int i = 0; i < nops; ++i) {
-            hip_check(hipStreamWaitEvent(b->streams[i], b->events[nops], 0), "fork");
-            matvec(*ops[i], trans[i], alpha[i], x[i], ldx[i], y[i], ldy[i], nrhs[i], b->streams[i]);
-            hip_check(hipEventRecord(b->events[i], b->streams[i]), "join");
-            hip_check(hipStreamWaitEvent(origin, b->events[i], 0), "join");
-        }
-    } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(origin, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
+    b->streams.resize(1, nullptr);
+    hip_check(hipStreamCreateWithFlags(&b->streams[0], hipStreamNonBlocking), "stream create");
+    hipStream_t cap = b->streams[0];
+    hip_check(hipGraphCreate(&b->graph, 0), "graph create");
+    for (int i = 0; i < nops; ++i) {
+        if (nrhs[i] == 1)
+            add_product_nodes(*ops[i], trans[i], alpha[i], x[i], y[i], b->graph, {}, cap);
+        else
+            add_captured(b->graph, {}, cap,
+                         [&] { matvec(*ops[i], trans[i], alpha[i], x[i], ldx[i], y[i], ldy[i], nrhs[i], cap); });
     }
-    hip_check(hipStreamEndCapture(origin, &b->graph), "end capture");
     hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
     return b;
 }

@@ -5,7 +5,8 @@
 // Every scalar of the iteration (rho, alpha, beta, the count and the stop
 // flag) lives in device memory, so the host only queues work: one iteration
 // is the H^2 product q = A p followed by five small vector kernels, and a
-// batch of check_every iterations is captured once into a HIP graph and
+// batch of check_every iterations is built once into a HIP graph (each
+// product with its nearfield and far field as parallel branches) and
 // replayed.  Inner products are two-stage reductions over a fixed grid
 // (partials per workgroup in a fixed slicing, then one workgroup sums them in
 // index order), so the same input gives the same bits.
@@ -13,6 +14,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <vector>
 
 #include "op.hpp"
 
@@ -283,16 +285,14 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     launch_fill_zero<double>(q, n, st);
     hip_check(hipGetLastError(), "cg start");
 
-    auto iterations = [&](hipStream_t s, int count) {
-        for (int k = 0; k < count; ++k) {
-            matvec(A, 0, 1.0, p, n, q, n, 1, s);
-            hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, s, p, q, n, part);
-            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(KT), 0, s, part, nb, S);
-            hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(KT), 0, s, x, r, p, q, n, S, part2);
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(KT), 0, s, part2, nb, S, hist);
-            hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(KT), 0, s, p, r, n, S);
-            hip_check(hipGetLastError(), "cg iteration");
-        }
+    // the vector work of one iteration after q = A p
+    auto update = [&](hipStream_t s) {
+        hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, s, p, q, n, part);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(KT), 0, s, part, nb, S);
+        hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(KT), 0, s, x, r, p, q, n, S, part2);
+        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(KT), 0, s, part2, nb, S, hist);
+        hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(KT), 0, s, p, r, n, S);
+        hip_check(hipGetLastError(), "cg iteration");
     };
     auto read_state = [&] {
         hip_check(hipMemcpyAsync(w.host, S, sizeof(CgState), hipMemcpyDeviceToHost, st), "state read");
@@ -303,19 +303,17 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     const int per = prm.check_every;
     CgState cur = read_state();
     if (cur.status == 0 && prm.use_graph) {
-        // the caller's stream may be the null stream, which cannot be
-        // captured: capture on a private stream, launch on the caller's
+        // one graph of `per` iterations: every product as prepare ->
+        // {nearfield, far field} -> scatter, then the vector kernels, each
+        // piece captured alone on a private stream (the caller's stream may
+        // be the null stream, which cannot be captured)
         hip_check(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking), "stream create");
-        hip_check(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal), "begin capture");
-        try {
-            iterations(w.cap, per);
-        } catch (...) {
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(w.cap, &g);
-            if (g) (void)hipGraphDestroy(g);
-            throw;
+        hip_check(hipGraphCreate(&w.graph, 0), "graph create");
+        std::vector<hipGraphNode_t> deps;
+        for (int k = 0; k < per; ++k) {
+            hipGraphNode_t prod = add_product_nodes(A, 0, 1.0, p, q, w.graph, deps, w.cap);
+            deps = {add_captured(w.graph, {prod}, w.cap, [&] { update(w.cap); })};
         }
-        hip_check(hipStreamEndCapture(w.cap, &w.graph), "end capture");
         hip_check(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0), "graph instantiate");
     }
     // every batch but a stopped one advances the count by `per`, so this bound
@@ -325,7 +323,10 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         if (w.exec)
             hip_check(hipGraphLaunch(w.exec, st), "graph launch");
         else
-            iterations(st, per);
+            for (int k = 0; k < per; ++k) {
+                matvec(A, 0, 1.0, p, n, q, n, 1, st);
+                update(st);
+            }
         cur = read_state();
     }
     if (cur.status == 0) fail(H2B_EDEVICE, "conjugate gradients did not reach a stop state");

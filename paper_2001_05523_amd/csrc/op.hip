@@ -446,8 +446,17 @@ static void join_side(Op &op, hipStream_t ns, hipStream_t st)
     hip_check(hipStreamWaitEvent(st, op.join, 0), "stream wait");
 }
 
+// The four pieces of one product.  Prepare clears the outputs and gathers x
+// into cluster order; Near (nearfield into ypn) and Far (forward
+// transformation, coupling, backward transformation into yp) both read only
+// xp and write disjoint buffers, so they may run concurrently; Finish adds
+// alpha (yp + ypn) to y in the caller's order.  `mark` records the phase
+// events of a timed product (NULL when untimed).
+enum class Piece { Prepare, Near, Far, Finish };
+
 template <typename F, typename C>
-static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
+static void product_piece(Op &op, int trans, double alpha, const double *x, double *y, Piece pc, hipStream_t st,
+                          hipEvent_t *ev)
 {
     const Basis &Bin = trans ? *op.rowb : *op.colb;
     const Basis &Bout = trans ? *op.colb : *op.rowb;
@@ -455,55 +464,91 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     const int64_t nout = trans ? op.ncols : op.nrows;
     double *xp = op.xp.as<double>(), *yp = op.yp.as<double>(), *ypn = op.ypn.as<double>();
     F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
-    hipEvent_t *ev = event_set(op, st);
-    auto mark = [&](int i, hipStream_t s) {
-        if (ev) hip_check(hipEventRecord(ev[i], s), "event record");
+    auto mark = [&](int i) {
+        if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
     };
-    launch_fill_zero<F>(yhat, Bout.hat_total, st);
-    launch_fill_zero<double>(yp, nout, st);
-    mark(0, st);
-    launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
-    mark(1, st);
-    // nearfield into ypn: on the side stream from here, or on st after the
-    // backward transformation
-    hipStream_t ns = fork_side(op, st);
-    auto nearfield = [&] {
-        launch_fill_zero<double>(ypn, nout, ns);
-        mark(5, ns);
+    switch (pc) {
+    case Piece::Prepare:
+        launch_fill_zero<F>(yhat, Bout.hat_total, st);
+        launch_fill_zero<double>(yp, nout, st);
+        mark(0);
+        launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
+        mark(1);
+        break;
+    case Piece::Near:
+        launch_fill_zero<double>(ypn, nout, st);
+        mark(5);
         if (op.sym)
-            symmetric_near_product(op, trans, xp, ypn, ns);
+            symmetric_near_product(op, trans, xp, ypn, st);
         else if (!trans)
             launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(), xp,
-                                                    ypn, true, ns, Role::Near);
+                                                    ypn, true, st, Role::Near);
         else if (op.has_R)
             launch_rowpanel<double, double, double>(op.near_R, 0, op.near_R.ngroups(),
-                                                    op.near_R_vals.as<double>(), xp, ypn, true, ns, Role::Near);
+                                                    op.near_R_vals.as<double>(), xp, ypn, true, st, Role::Near);
         else
             launch_colpanel<double, double, double>(op.near_T, 0, op.near_T.ngroups(), op.near_vals.as<double>(),
-                                                    xp, ypn, ns, Role::Near);
-        mark(6, ns);
-    };
-    if (ns != st) nearfield();
-    // far field into yp on the caller's stream
-    forward<F>(Bin, xp, xhat, st);
-    mark(2, st);
-    if (!trans)
-        launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, true, st,
-                                 Role::Coupling);
-    else if (op.has_R)
-        launch_rowpanel<C, F, F>(op.cpl_R, 0, op.cpl_R.ngroups(), op.cpl_R_vals.as<C>(), xhat, yhat, true, st,
-                                 Role::Coupling);
-    else
-        launch_colpanel<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, st,
-                                 Role::Coupling);
-    mark(3, st);
-    backward<F>(Bout, yhat, yp, st);
-    mark(4, st);
-    if (ns == st) nearfield();
+                                                    xp, ypn, st, Role::Near);
+        mark(6);
+        break;
+    case Piece::Far:
+        forward<F>(Bin, xp, xhat, st);
+        mark(2);
+        if (!trans)
+            launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, true, st,
+                                     Role::Coupling);
+        else if (op.has_R)
+            launch_rowpanel<C, F, F>(op.cpl_R, 0, op.cpl_R.ngroups(), op.cpl_R_vals.as<C>(), xhat, yhat, true,
+                                     st, Role::Coupling);
+        else
+            launch_colpanel<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, st,
+                                     Role::Coupling);
+        mark(3);
+        backward<F>(Bout, yhat, yp, st);
+        mark(4);
+        break;
+    case Piece::Finish:
+        launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, ypn, y, nout, st);
+        mark(8);
+        break;
+    }
+}
+
+template <typename F, typename C>
+static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
+{
+    hipEvent_t *ev = event_set(op, st);
+    product_piece<F, C>(op, trans, alpha, x, y, Piece::Prepare, st, ev);
+    // nearfield on the side stream from here, or on st after the far field
+    hipStream_t ns = fork_side(op, st);
+    if (ns != st) product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, ns, ev);
+    product_piece<F, C>(op, trans, alpha, x, y, Piece::Far, st, ev);
+    if (ns == st) product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, st, ev);
     join_side(op, ns, st);
-    mark(7, st);
-    launch_scatter_add(Bout.perm_dev, nout, 1, alpha, yp, ypn, y, nout, st);
-    mark(8, st);
+    if (ev) hip_check(hipEventRecord(ev[7], st), "event record");
+    product_piece<F, C>(op, trans, alpha, x, y, Piece::Finish, st, ev);
+}
+
+template <typename F, typename C>
+static hipGraphNode_t add_product_impl(Op &op, int trans, double alpha, const double *x, double *y, hipGraph_t g,
+                                       const std::vector<hipGraphNode_t> &deps, hipStream_t cap)
+{
+    auto piece = [&](Piece pc) { return [&, pc] { product_piece<F, C>(op, trans, alpha, x, y, pc, cap, nullptr); }; };
+    hipGraphNode_t prep = add_captured(g, deps, cap, piece(Piece::Prepare));
+    hipGraphNode_t near = add_captured(g, {prep}, cap, piece(Piece::Near));
+    hipGraphNode_t far = add_captured(g, {prep}, cap, piece(Piece::Far));
+    return add_captured(g, {near, far}, cap, piece(Piece::Finish));
+}
+
+hipGraphNode_t add_product_nodes(Op &op, int trans, double alpha, const double *x, double *y, hipGraph_t g,
+                                 const std::vector<hipGraphNode_t> &deps, hipStream_t cap)
+{
+    check_product_args(op, trans, x, trans ? op.nrows : op.ncols, y, trans ? op.ncols : op.nrows, 1);
+    switch (op.params.farfield_dtype) {
+    case H2B_F64: return add_product_impl<double, double>(op, trans, alpha, x, y, g, deps, cap);
+    case H2B_F32: return add_product_impl<float, float>(op, trans, alpha, x, y, g, deps, cap);
+    default: return add_product_impl<float, bf16_t>(op, trans, alpha, x, y, g, deps, cap);
+    }
 }
 
 // ------------------------------------------------ many right-hand sides
