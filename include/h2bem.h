@@ -210,7 +210,8 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
  * operator's own that is forked from hip_stream after x is read into the
  * operator's work vector and joined back before y is written, so the call is
  * ordered on hip_stream like a single kernel.  While hip_stream is being
- * captured into a graph, the whole product stays on hip_stream.  The work vectors belong to the
+ * captured into a graph, the whole product stays on hip_stream, with the
+ * nearfield and the far field as two parallel branches of the graph.  The work vectors belong to the
  * operator: products on one operator must not overlap (same stream, or ordered
  * by the caller).  x and y must not overlap.
  * Errors: H2B_EINVAL (NULL pointers, nrhs < 1 or > 64, ld too small), H2B_EDEVICE. */
@@ -218,10 +219,9 @@ h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
 
 /* Batched products over several operators (e.g. meshes of different sizes):
- * builds y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  The
- * products of different operators are concurrent branches of the graph, and
- * a single-vector product (nrhs_i = 1) is itself two branches, nearfield and
- * far field, between the gather of x_i and the write of y_i.
+ * captures y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  The
+ * products of different operators are concurrent branches of the graph; each
+ * product keeps its phases in sequence inside its branch.
  * The arrays give per-operator arguments as for h2b_matvec; the device
  * vectors are bound at creation and must stay valid while the batch exists.
  * Creation checks every argument first and allocates each operator's work
@@ -324,9 +324,9 @@ h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, 
  * ||r_k||_2 <= tol ||b||_2 (r_k the updated residual; absolute when b = 0),
  * after max_iter iterations, or on breakdown (p^T q not positive or not
  * finite).  Every scalar of the iteration stays on the device: the host
- * queues check_every iterations at a time (built once into a HIP graph, in
- * which each product runs its nearfield and far field as parallel branches,
- * and replayed when use_graph = 1) and then reads the state.  The iterations
+ * queues check_every iterations at a time (captured once into a HIP graph,
+ * in which each product runs its nearfield and far field as parallel
+ * branches, and replayed when use_graph = 1) and then reads the state.  The iterations
  * queued after the stopping one change nothing (x, r and the count are
  * frozen), so the result does not depend on check_every or use_graph.  The
  * products of A inside the iteration run with A's precision settings (a

@@ -1,13 +1,17 @@
-// Batched products over several operators (meshes of different sizes) built
-// once into a hipGraph: the products of different meshes are independent
-// branches of the graph, and inside each single-vector product the nearfield
-// and the far field are two more parallel branches (prepare -> {nearfield,
-// far field} -> scatter).  Every piece is captured alone on one private
-// stream and added as a child-graph node, so no capture spans two streams.
-// One graph launch runs the whole batch.
+// Batched products over several operators (meshes of different sizes)
+// captured once into a hipGraph on one stream: each operator's product starts
+// a new root of the graph (the stream's capture dependencies are cleared
+// before it), so the products of different meshes are independent branches.
+// Inside the batch each product keeps its phases in sequence: splitting every
+// product further into nearfield and far-field branches made the graph of 16
+// meshes (2,048 to 32,768 triangles) three times slower on the MI355X (3.3 ms
+// against 1.1 ms), while a product captured alone gains from the split.  The
+// capture ends after every branch; one graph launch runs the whole batch.
 #include <hip/hip_runtime.h>
 
 #include <set>
+#include <utility>
+#include <vector>
 
 #include "op.hpp"
 
@@ -37,21 +41,43 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
         prepare_product(*ops[i], nrhs[i]);
     }
     // the caller's stream may be the null stream, which cannot be captured:
-    // capture the pieces on a private stream and launch the graph on the
-    // caller's stream later
+    // capture on a private stream and launch the graph on the caller's
+    // stream later
     (void)st;
     auto b = std::make_unique<Batch>();
     b->streams.resize(1, nullptr);
     hip_check(hipStreamCreateWithFlags(&b->streams[0], hipStreamNonBlocking), "stream create");
     hipStream_t cap = b->streams[0];
-    hip_check(hipGraphCreate(&b->graph, 0), "graph create");
+    // the products stay sequential inside the capture (overlap off), restored
+    // on every exit
+    struct OverlapOff {
+        std::vector<std::pair<Op *, bool>> saved;
+        ~OverlapOff()
+        {
+            for (auto &o : saved) o.first->overlap = o.second;
+        }
+    } guard;
     for (int i = 0; i < nops; ++i) {
-        if (nrhs[i] == 1)
-            add_product_nodes(*ops[i], trans[i], alpha[i], x[i], y[i], b->graph, {}, cap);
-        else
-            add_captured(b->graph, {}, cap,
-                         [&] { matvec(*ops[i], trans[i], alpha[i], x[i], ldx[i], y[i], ldy[i], nrhs[i], cap); });
+        guard.saved.push_back({ops[i], ops[i]->overlap});
+        ops[i]->overlap = false;
     }
+    hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+        std::vector<hipGraphNode_t> ends;
+        for (int i = 0; i < nops; ++i) {
+            if (i > 0) set_capture_tail(cap, {});
+            matvec(*ops[i], trans[i], alpha[i], x[i], ldx[i], y[i], ldy[i], nrhs[i], cap);
+            const std::vector<hipGraphNode_t> e = capture_tail(cap);
+            ends.insert(ends.end(), e.begin(), e.end());
+        }
+        set_capture_tail(cap, ends);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(cap, &b->graph), "end capture");
     hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
     return b;
 }

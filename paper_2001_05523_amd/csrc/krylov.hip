@@ -5,7 +5,7 @@
 // Every scalar of the iteration (rho, alpha, beta, the count and the stop
 // flag) lives in device memory, so the host only queues work: one iteration
 // is the H^2 product q = A p followed by five small vector kernels, and a
-// batch of check_every iterations is built once into a HIP graph (each
+// batch of check_every iterations is captured once into a HIP graph (each
 // product with its nearfield and far field as parallel branches) and
 // replayed.  Inner products are two-stage reductions over a fixed grid
 // (partials per workgroup in a fixed slicing, then one workgroup sums them in
@@ -14,7 +14,6 @@
 
 #include <chrono>
 #include <cmath>
-#include <vector>
 
 #include "op.hpp"
 
@@ -303,17 +302,24 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     const int per = prm.check_every;
     CgState cur = read_state();
     if (cur.status == 0 && prm.use_graph) {
-        // one graph of `per` iterations: every product as prepare ->
-        // {nearfield, far field} -> scatter, then the vector kernels, each
-        // piece captured alone on a private stream (the caller's stream may
-        // be the null stream, which cannot be captured)
+        // one graph of `per` iterations, captured on a private stream (the
+        // caller's stream may be the null stream, which cannot be captured);
+        // inside it every product runs its nearfield and far field as
+        // parallel branches
         hip_check(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking), "stream create");
-        hip_check(hipGraphCreate(&w.graph, 0), "graph create");
-        std::vector<hipGraphNode_t> deps;
-        for (int k = 0; k < per; ++k) {
-            hipGraphNode_t prod = add_product_nodes(A, 0, 1.0, p, q, w.graph, deps, w.cap);
-            deps = {add_captured(w.graph, {prod}, w.cap, [&] { update(w.cap); })};
+        hip_check(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+            for (int k = 0; k < per; ++k) {
+                matvec(A, 0, 1.0, p, n, q, n, 1, w.cap);
+                update(w.cap);
+            }
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(w.cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
         }
+        hip_check(hipStreamEndCapture(w.cap, &w.graph), "end capture");
         hip_check(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0), "graph instantiate");
     }
     // every batch but a stopped one advances the count by `per`, so this bound

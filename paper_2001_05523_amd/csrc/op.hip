@@ -425,8 +425,8 @@ static hipEvent_t *event_set(Op &op, hipStream_t st)
 
 // Stream of the nearfield: the operator's side stream, which waits for
 // everything queued on st so far (fork), or st itself when overlap is off or
-// while st is being captured into a graph (a captured product stays on the
-// captured stream).
+// while st is being captured into a graph (no capture spans two streams: a
+// captured product forms its branches on the captured stream).
 static hipStream_t fork_side(Op &op, hipStream_t st)
 {
     if (!op.overlap) return st;
@@ -514,9 +514,43 @@ static void product_piece(Op &op, int trans, double alpha, const double *x, doub
     }
 }
 
+std::vector<hipGraphNode_t> capture_tail(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipGraphNode_t *d = nullptr;
+    size_t nd = 0;
+    hip_check(hipStreamGetCaptureInfo_v2(st, &cs, nullptr, nullptr, &d, &nd), "capture info");
+    return std::vector<hipGraphNode_t>(d, d + nd);
+}
+
+void set_capture_tail(hipStream_t st, std::vector<hipGraphNode_t> deps)
+{
+    hip_check(hipStreamUpdateCaptureDependencies(st, deps.empty() ? nullptr : deps.data(), deps.size(),
+                                                 hipStreamSetCaptureDependencies),
+              "capture dependencies");
+}
+
 template <typename F, typename C>
 static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
 {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cs), "capture status");
+    if (cs != hipStreamCaptureStatusNone && op.overlap) {
+        // captured into a graph: the nearfield and the far field become two
+        // parallel branches after the gather, made on this one stream by
+        // resetting what the next captured work depends on
+        product_piece<F, C>(op, trans, alpha, x, y, Piece::Prepare, st, nullptr);
+        const std::vector<hipGraphNode_t> prep = capture_tail(st);
+        product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, st, nullptr);
+        std::vector<hipGraphNode_t> ends = capture_tail(st);
+        set_capture_tail(st, prep);
+        product_piece<F, C>(op, trans, alpha, x, y, Piece::Far, st, nullptr);
+        const std::vector<hipGraphNode_t> far = capture_tail(st);
+        ends.insert(ends.end(), far.begin(), far.end());
+        set_capture_tail(st, ends);
+        product_piece<F, C>(op, trans, alpha, x, y, Piece::Finish, st, nullptr);
+        return;
+    }
     hipEvent_t *ev = event_set(op, st);
     product_piece<F, C>(op, trans, alpha, x, y, Piece::Prepare, st, ev);
     // nearfield on the side stream from here, or on st after the far field
@@ -527,28 +561,6 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
     join_side(op, ns, st);
     if (ev) hip_check(hipEventRecord(ev[7], st), "event record");
     product_piece<F, C>(op, trans, alpha, x, y, Piece::Finish, st, ev);
-}
-
-template <typename F, typename C>
-static hipGraphNode_t add_product_impl(Op &op, int trans, double alpha, const double *x, double *y, hipGraph_t g,
-                                       const std::vector<hipGraphNode_t> &deps, hipStream_t cap)
-{
-    auto piece = [&](Piece pc) { return [&, pc] { product_piece<F, C>(op, trans, alpha, x, y, pc, cap, nullptr); }; };
-    hipGraphNode_t prep = add_captured(g, deps, cap, piece(Piece::Prepare));
-    hipGraphNode_t near = add_captured(g, {prep}, cap, piece(Piece::Near));
-    hipGraphNode_t far = add_captured(g, {prep}, cap, piece(Piece::Far));
-    return add_captured(g, {near, far}, cap, piece(Piece::Finish));
-}
-
-hipGraphNode_t add_product_nodes(Op &op, int trans, double alpha, const double *x, double *y, hipGraph_t g,
-                                 const std::vector<hipGraphNode_t> &deps, hipStream_t cap)
-{
-    check_product_args(op, trans, x, trans ? op.nrows : op.ncols, y, trans ? op.ncols : op.nrows, 1);
-    switch (op.params.farfield_dtype) {
-    case H2B_F64: return add_product_impl<double, double>(op, trans, alpha, x, y, g, deps, cap);
-    case H2B_F32: return add_product_impl<float, float>(op, trans, alpha, x, y, g, deps, cap);
-    default: return add_product_impl<float, bf16_t>(op, trans, alpha, x, y, g, deps, cap);
-    }
 }
 
 // ------------------------------------------------ many right-hand sides

@@ -127,36 +127,11 @@ void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, c
 void prepare_product(Op &op, int nrhs);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);
-// Captures the work `fn` queues on the private stream cap into a graph of its
-// own and adds it to g as a child-graph node after the nodes deps.
-template <typename Fn>
-hipGraphNode_t add_captured(hipGraph_t g, const std::vector<hipGraphNode_t> &deps, hipStream_t cap, Fn &&fn)
-{
-    hipGraph_t child = nullptr;
-    hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    try {
-        fn();
-    } catch (...) {
-        (void)hipStreamEndCapture(cap, &child);
-        if (child) (void)hipGraphDestroy(child);
-        throw;
-    }
-    hip_check(hipStreamEndCapture(cap, &child), "end capture");
-    hipGraphNode_t node = nullptr;
-    const hipError_t e =
-        hipGraphAddChildGraphNode(&node, g, deps.empty() ? nullptr : deps.data(), deps.size(), child);
-    (void)hipGraphDestroy(child);
-    hip_check(e, "child graph node");
-    return node;
-}
-
-// Adds the single-vector product y += alpha op(A) x to the graph g after the
-// nodes deps, as child graphs captured one by one on the private stream cap:
-// prepare, then nearfield and far field as two parallel branches, then the
-// final scatter (returned: later work depends on it).  The operator's
-// nearfield and far field overlap in the graph without a cross-stream capture.
-hipGraphNode_t add_product_nodes(Op &op, int trans, double alpha, const double *x, double *y, hipGraph_t g,
-                                 const std::vector<hipGraphNode_t> &deps, hipStream_t cap);
+// Nodes the next work captured on st will depend on, and their replacement
+// (st must be capturing): with these a single captured stream forms parallel
+// branches of the graph.
+std::vector<hipGraphNode_t> capture_tail(hipStream_t st);
+void set_capture_tail(hipStream_t st, std::vector<hipGraphNode_t> deps);
 
 // A captured batch of products (one graph, one forked stream per operator).
 struct Batch {
