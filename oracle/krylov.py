@@ -1,5 +1,6 @@
-"""Test infrastructure only: the Dirichlet-to-Neumann system and the conjugate
-gradient method, dense and in double precision (small meshes only).
+"""Test infrastructure only: the Dirichlet-to-Neumann and Neumann-to-Dirichlet
+systems and the conjugate gradient method, dense and in double precision
+(small meshes only).
 
 * Mixed mass matrix (Section 1): m_ij = int psi_i phi_j for the piecewise
   constant psi_i (triangles) and the piecewise linear hat functions phi_j
@@ -15,6 +16,19 @@ gradient method, dense and in double precision (small meshes only).
   eps_slv: stop at the first iterate whose residual satisfies
   ||b - A x_k||_2 <= tol ||b||_2, where the residual is the one the
   recurrence updates.
+* Hypersingular matrix (Section 1, eq. for w_ij, set up through the
+  alternative representation based on the single-layer operator that the
+  paper cites): for the hat functions on flat triangles,
+  w_ij = sum over triangle pairs of <curl phi_i|tau, curl phi_j|tau'> g_{tau tau'},
+  with g_{tau tau'} the single-layer entries of the triangle indicators and
+  the surface curl n x grad phi constant on each triangle; on tau with
+  corners (a, b, c) in counter-clockwise order, curl phi_a = (x_b - x_c) / (2|tau|)
+  and cyclically.  So W = sum_d C_d^T G C_d with (C_d)_{tau j} the d-th
+  component of curl phi_j on tau.
+* Neumann-to-Dirichlet system (Section 1, eq. (matrix_ntd)):
+  W u = (M^T/2 - K^T) t.  W annihilates constants, so the discrete Dirichlet
+  data are fixed up to a constant; the direct solve here picks the solution
+  with int u_h = 0 (an added Lagrange multiplier).
 * The test functions of Section 5: u1(x) = x1^2 - x3^2, u2 = g(., y1) and
   u3 = g(., y2) with y1 = (1.2, 1.2, 1.2), y2 = (1.0, 0.25, 1.0), all
   harmonic inside the unit sphere, and the L2 error of a piecewise constant
@@ -145,3 +159,87 @@ def neumann_l2_error(verts, tris, t, grad_u, q=6):
     dn = np.einsum("ikd,id->ik", grad_u(X), n)
     err2 = np.einsum("ik,k,i->", (t[:, None] - dn) ** 2, W, 2.0 * area)
     return math.sqrt(err2)
+
+
+# ------------------------------------------------ hypersingular operator
+
+def curl_matrices(verts, tris):
+    """Dense C_0, C_1, C_2 (nt x nv each): (C_d)_{tau j} = d-th component of
+    the surface curl of the hat function phi_j on triangle tau."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    area, _ = _areas_normals(verts, tris)
+    C = np.zeros((3, len(tris), len(verts)))
+    for i, (a, b, c) in enumerate(tris):
+        for j, nxt, prv in ((a, b, c), (b, c, a), (c, a, b)):
+            C[:, i, j] += (verts[nxt] - verts[prv]) / (2.0 * area[i])
+    return C
+
+
+def hypersingular_from_slp(G, C):
+    """W = sum_d C_d^T G C_d."""
+    return sum(C[d].T @ G @ C[d] for d in range(3))
+
+
+def p1_mass_matrix(verts, tris):
+    """int phi_i phi_j: |tau|/6 on the diagonal and |tau|/12 off it, per triangle."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    area, _ = _areas_normals(verts, tris)
+    M1 = np.zeros((len(verts), len(verts)))
+    for i, tri in enumerate(tris):
+        for a in tri:
+            for b in tri:
+                M1[a, b] += area[i] / (6.0 if a == b else 12.0)
+    return M1
+
+
+def ntd_rhs(K, M, t):
+    """Right-hand side (M^T/2 - K^T) t of eq. (matrix_ntd)."""
+    return 0.5 * (M.T @ t) - K.T @ t
+
+
+def ntd_solve(W, K, M, t):
+    """Dirichlet coefficients u with W u = (M^T/2 - K^T) t and int u_h = 0
+    (dense direct solve of the system bordered by the P1 integrals)."""
+    w1 = M.sum(axis=0)  # int phi_j
+    n = W.shape[0]
+    A = np.zeros((n + 1, n + 1))
+    A[:n, :n] = W
+    A[:n, n] = w1
+    A[n, :n] = w1
+    rhs = np.concatenate([ntd_rhs(K, M, t), [0.0]])
+    return np.linalg.solve(A, rhs)[:n]
+
+
+def dirichlet_l2_error(verts, tris, uh, u, q=6):
+    """|| (u_h - mean u_h) - (u - mean u) ||_{L2(Gamma)} for the P1 function
+    u_h (vertex coefficients) against the function u on the flat triangles
+    (both taken with zero mean: the Neumann data fix u only up to a constant)."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    area, _ = _areas_normals(verts, tris)
+    U, W = triangle_rule(q)
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    X = a[:, None, :] + U[None, :, :1] * (b - a)[:, None, :] + U[None, :, 1:2] * (c - b)[:, None, :]
+    # barycentric weights of x = a + u1 (b - a) + u2 (c - b): (1 - u1, u1 - u2, u2)
+    lam = np.stack([1.0 - U[:, 0], U[:, 0] - U[:, 1], U[:, 1]], axis=1)
+    vh = np.einsum("kc,ic->ik", lam, uh[tris])
+    vu = u(X)
+    wts = W[None, :] * (2.0 * area)[:, None]
+    tot = wts.sum()
+    d = (vh - (vh * wts).sum() / tot) - (vu - (vu * wts).sum() / tot)
+    return math.sqrt(float((d * d * wts).sum()))
+
+
+def neumann_projection(verts, tris, grad_u, q=6):
+    """P0 L2 projection of the normal derivative <grad u, n_tau>: its mean
+    over every flat triangle (collapsed q x q Gauss rule)."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris)
+    _, n = _areas_normals(verts, tris)
+    U, W = triangle_rule(q)
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    X = a[:, None, :] + U[None, :, :1] * (b - a)[:, None, :] + U[None, :, 1:2] * (c - b)[:, None, :]
+    dn = np.einsum("ikd,id->ik", grad_u(X), n)
+    return (dn * W[None, :]).sum(axis=1) / W.sum()

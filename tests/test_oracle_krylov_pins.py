@@ -1,14 +1,17 @@
-"""Pins of the oracle's mass matrix, conjugate gradient method and
-Dirichlet-to-Neumann solve against facts that do not come from the oracle
-itself: exact integration of linear functions, finite termination and the
-energy-norm optimality of CG, closed-form Neumann data of harmonic functions
-and the first-order L2 convergence that Section 5 reports for the
-Dirichlet-to-Neumann problem."""
+"""Pins of the oracle's mass matrix, conjugate gradient method,
+Dirichlet-to-Neumann solve, hypersingular matrix and Neumann-to-Dirichlet
+solve against facts that do not come from the oracle itself: exact
+integration of linear functions, finite termination and the energy-norm
+optimality of CG, closed-form Neumann data of harmonic functions, the
+eigenvalues of the hypersingular operator on the sphere, and the L2
+convergence orders that Section 5 states (O(h) for the Neumann data, O(h^2)
+for the Dirichlet data)."""
 import math
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from oracle import krylov
 
@@ -160,3 +163,82 @@ def test_dtn_paper_functions_converge_first_order():
         assert e[0] > e[1] > e[2], (name, e)
         rate = math.log2(e[1] / e[2])
         assert 0.8 <= rate <= 1.6, (name, e, rate)
+
+
+# ------------------------------------------------ hypersingular, Neumann-to-Dirichlet
+
+def test_surface_curls_of_linear_functions():
+    """On a flat triangle the surface curl n x grad_Gamma u of u = a . x is
+    n_tau x a, and constants have zero curl; three components per triangle
+    fix the three corner entries of each row of C_d."""
+    v, t = synth.perturbed_sphere(4, seed=5)
+    _, n, _ = _geom(v, t)
+    C = krylov.curl_matrices(v, t)
+    a = np.array([0.3, -0.8, 0.5])
+    got = np.stack([C[d] @ (v @ a) for d in range(3)], axis=1)
+    assert np.max(np.abs(got - np.cross(n, a))) <= 1e-13
+    assert np.max(np.abs(np.stack([C[d] @ np.ones(len(v)) for d in range(3)]))) <= 1e-13
+    b = np.array([-0.1, 0.4, 0.9])
+    got = np.stack([C[d] @ (v @ b) for d in range(3)], axis=1)
+    assert np.max(np.abs(got - np.cross(n, b))) <= 1e-13
+
+
+def test_hypersingular_spectrum_on_the_sphere():
+    """The hypersingular operator of the unit sphere has the spherical
+    harmonics of degree l as eigenfunctions with eigenvalue l(l+1)/(2l+1)
+    (classical; not printed in the paper).  Rayleigh quotients of the P1
+    interpolants of degree-1, 2 and 3 harmonics approach it at second order,
+    and W annihilates constants."""
+    harmonics = ((1, lambda p: p[:, 2]), (2, lambda p: p[:, 0] * p[:, 1]), (3, lambda p: p[:, 0] * p[:, 1] * p[:, 2]))
+    rel = []
+    for s in (4, 8):
+        v, t = synth.octa_sphere(s)
+        W = krylov.hypersingular_from_slp(oracle.slp_dense(v, t, 4), krylov.curl_matrices(v, t))
+        M1 = krylov.p1_mass_matrix(v, t)
+        assert np.max(np.abs(W @ np.ones(len(v)))) <= 1e-14 * np.max(np.abs(W))
+        row = []
+        for l, f in harmonics:
+            c = f(v)
+            row.append(abs((c @ W @ c) / (c @ M1 @ c) / (l * (l + 1) / (2 * l + 1)) - 1))
+        rel.append(row)
+    for l in range(3):
+        assert rel[1][l] < 0.015 and rel[0][l] / rel[1][l] > 3.0, rel
+
+
+def test_ntd_reproduces_linear_dirichlet_data():
+    """For linear u the Neumann data a . n_tau are exact in P0 and u is its
+    own P1 interpolant; the hypersingular equation of Green's formula holds
+    on the polyhedron, so the solution of eq. (matrix_ntd) with zero mean is
+    the zero-mean nodal u up to quadrature error, falling exponentially in q."""
+    v, t = synth.octa_sphere(4)
+    _, n, _ = _geom(v, t)
+    a = np.array([1.0, -0.5, 0.25])
+    err = []
+    for q in (4, 8, 12):
+        G, K, M = krylov.dtn_matrices(v, t, q)
+        W = krylov.hypersingular_from_slp(G, krylov.curl_matrices(v, t))
+        u = krylov.ntd_solve(W, K, M, n @ a)
+        ex = v @ a
+        w1 = M.sum(axis=0)
+        ex = ex - (w1 @ ex) / w1.sum()
+        err.append(np.max(np.abs(u - ex)) / np.max(np.abs(ex)))
+    assert err[0] > 100 * err[1] > 1e4 * err[2], err
+    assert err[2] <= 1e-10, err
+
+
+def test_ntd_paper_functions_converge_second_order():
+    """Section 5: the Dirichlet data of u1, u2, u3 computed from eq.
+    (matrix_ntd) with the P0 projection of their Neumann data converge in L2
+    at O(h^2) (observed order between s = 8 and 16)."""
+    errs = {name: [] for name in krylov.TEST_FUNCTIONS}
+    for s in (4, 8, 16):
+        v, t = synth.octa_sphere(s)
+        G, K, M = krylov.dtn_matrices(v, t, 4)
+        W = krylov.hypersingular_from_slp(G, krylov.curl_matrices(v, t))
+        for name, (u, grad) in krylov.TEST_FUNCTIONS.items():
+            uh = krylov.ntd_solve(W, K, M, krylov.neumann_projection(v, t, grad))
+            errs[name].append(krylov.dirichlet_l2_error(v, t, uh, u))
+    for name, e in errs.items():
+        assert e[0] > e[1] > e[2], (name, e)
+        rate = math.log2(e[1] / e[2])
+        assert 1.7 <= rate <= 2.5, (name, e, rate)
