@@ -313,6 +313,22 @@ h2b_status h2b_op_set_overlap(h2b_op op, int enable);
 h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, double *y,
                            void *hip_stream);
 
+/* Hypersingular matrix W (Section 1, eq. for w_ij), set up through its
+ * representation by the single-layer operator that the paper uses: for the
+ * hat functions on flat triangles w_ij is the sum over triangle pairs of
+ * <curl phi_i on tau, curl phi_j on tau'> times the single-layer entry
+ * g_{tau tau'}, i.e. W = sum_d C_d^T G C_d, where the surface curl
+ * n x grad phi_j is constant on each triangle (corners (a, b, c)
+ * counter-clockwise: curl phi_a = (x_b - x_c) / (2 |tau|), cyclically).
+ * y += alpha W x with x, y device arrays of nv doubles (vertex order).  G is
+ * the H^2 single-layer operator of the mesh (any precision settings); one
+ * call is two small curl kernels around one product of G with three
+ * right-hand sides.  The first call allocates 6 nt doubles of work vectors
+ * on the operator.  W annihilates constants.  Runs asynchronously on
+ * hip_stream.  Errors: H2B_EINVAL if G is not the single-layer operator, for
+ * NULL or overlapping x and y. */
+h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, double *y, void *hip_stream);
+
 /* Conjugate gradients for A x = b with the H^2 product of a square operator
  * (meant for the symmetric positive definite single-layer matrix G of eq.
  * (matrix_dtn); the Krylov solver of the experiments in Section 5).
@@ -332,20 +348,35 @@ h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, 
  * products of A inside the iteration run with A's precision settings (a
  * lower-precision far field makes CG solve the perturbed system).
  *
+ * With form = H2B_FORM_HYPERSINGULAR the operator is instead the
+ * hypersingular matrix W built from the single-layer operator A = G (see
+ * h2b_hypersingular_matvec), for the Neumann-to-Dirichlet system
+ * W u = (M^T/2 - K^T) t of eq. (matrix_ntd).  W is only semi-definite
+ * (constants span its null space) and such a right-hand side is orthogonal
+ * to the constants only up to quadrature error, so b is first replaced by
+ * b - c w1 with w1_j = int phi_j and c = 1^T b / 1^T w1 (the consistent
+ * system of the solve bordered by w1), CG runs on that (the residuals and
+ * tol refer to it), and the solution is returned with int u_h = w1^T x = 0.
+ *
  * b: device array of n doubles; x: device array of n doubles, the initial
  * guess on entry (ignored and set to 0 when zero_guess = 1) and the last
- * iterate on return; n = rows = columns of A.  history: NULL, or a host array
+ * iterate on return; n = rows = columns of A (the number of vertices for the
+ * hypersingular form).  history: NULL, or a host array
  * of max_iter + 1 doubles receiving ||r_k|| / ||b|| for k = 0..iterations.
  * Work vectors (3 n doubles plus small state) are allocated per call.  The
  * call synchronises hip_stream and returns when the solve has ended.
- * Errors: H2B_EINVAL for a non-square operator, NULL or overlapping b and x,
- * tol < 0 or not finite, max_iter < 0, check_every < 1. */
+ * Errors: H2B_EINVAL for a non-square operator (not the single-layer
+ * operator for the hypersingular form), an unknown form, NULL or overlapping
+ * b and x, tol < 0 or not finite, max_iter < 0, check_every < 1. */
+typedef enum { H2B_FORM_PRODUCT = 0, H2B_FORM_HYPERSINGULAR = 1 } h2b_cg_form;
+
 typedef struct {
     double tol;        /* relative residual to reach (default 1e-8) */
     int max_iter;      /* iteration limit (default 1000) */
     int check_every;   /* iterations queued between two reads of the state (default 8) */
     int use_graph;     /* 1: replay a HIP graph of check_every iterations (default 1) */
     int zero_guess;    /* 1: start from x = 0 without the initial product (default 1) */
+    int form;          /* h2b_cg_form: the operator's product (default) or W built from G */
 } h2b_cg_params;
 
 typedef enum { H2B_CG_CONVERGED = 1, H2B_CG_BREAKDOWN = 2, H2B_CG_MAXITER = 3 } h2b_cg_status;

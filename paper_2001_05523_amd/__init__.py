@@ -56,7 +56,7 @@ class h2b_op_stats(ctypes.Structure):
 
 class h2b_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int), ("form", ctypes.c_int)]
 
 
 class h2b_cg_result(ctypes.Structure):
@@ -65,6 +65,8 @@ class h2b_cg_result(ctypes.Structure):
 
 
 H2B_CG_CONVERGED, H2B_CG_BREAKDOWN, H2B_CG_MAXITER = 1, 2, 3
+H2B_FORM_PRODUCT, H2B_FORM_HYPERSINGULAR = 0, 1
+_FORMS = {"product": H2B_FORM_PRODUCT, "hypersingular": H2B_FORM_HYPERSINGULAR}
 CG_STATUS = {H2B_CG_CONVERGED: "converged", H2B_CG_BREAKDOWN: "breakdown", H2B_CG_MAXITER: "max_iter"}
 
 
@@ -98,6 +100,7 @@ _SIGS = {
     "h2b_mass_matvec": ([_vp, ctypes.c_int, _dbl, _vp, _vp, _vp], ctypes.c_int),
     "h2b_cg_params_default": ([_P(h2b_cg_params)], None),
     "h2b_cg_solve": ([_vp, _vp, _vp, _P(h2b_cg_params), _P(h2b_cg_result), _vp, _vp], ctypes.c_int),
+    "h2b_hypersingular_matvec": ([_vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -300,21 +303,40 @@ class Operator:
                                _vp(y.data_ptr()), _stream_ptr(stream)))
         return y
 
+    def hypersingular_matvec(self, x, y, alpha=1.0, stream=None):
+        """y += alpha W x for the hypersingular matrix W built from this
+        single-layer operator (x, y: one entry per vertex)."""
+        if self.kernel != H2B_SLP:
+            raise ValueError("the hypersingular product needs the single-layer operator")
+        _vector(x, self.mesh.nv, "x")
+        _vector(y, self.mesh.nv, "y")
+        _check(h2b_hypersingular_matvec(self.handle, float(alpha), _vp(x.data_ptr()), _vp(y.data_ptr()),
+                                        _stream_ptr(stream)))
+        return y
+
     def cg(self, b, x, tol=1e-8, max_iter=1000, check_every=8, use_graph=True, zero_guess=True,
-           history=False, stream=None):
+           history=False, form="product", stream=None):
         """Conjugate gradients for A x = b (A square, symmetric positive
-        definite: the single-layer matrix G).  x holds the initial guess
-        (unless zero_guess) and receives the solution.  Returns a dict with
-        iterations, status, rel_residual, solve_ms and, with history, the
-        relative residual norms of iterations 0..iterations."""
-        if self.shape[0] != self.shape[1]:
-            raise ValueError("conjugate gradients need a square operator")
-        _vector(b, self.shape[0], "b")
-        _vector(x, self.shape[0], "x")
+        definite: the single-layer matrix G), or with form="hypersingular"
+        for W x = b, W built from this single-layer operator.  x holds the
+        initial guess (unless zero_guess) and receives the solution.  Returns
+        a dict with iterations, status, rel_residual, solve_ms and, with
+        history, the relative residual norms of iterations 0..iterations."""
+        if form == "hypersingular":
+            if self.kernel != H2B_SLP:
+                raise ValueError("the hypersingular form needs the single-layer operator")
+            n = self.mesh.nv
+        else:
+            if self.shape[0] != self.shape[1]:
+                raise ValueError("conjugate gradients need a square operator")
+            n = self.shape[0]
+        _vector(b, n, "b")
+        _vector(x, n, "x")
         p = h2b_cg_params()
         h2b_cg_params_default(ctypes.byref(p))
         p.tol, p.max_iter, p.check_every = float(tol), int(max_iter), int(check_every)
         p.use_graph, p.zero_guess = int(bool(use_graph)), int(bool(zero_guess))
+        p.form = _FORMS[form]
         r = h2b_cg_result()
         hist = np.zeros(max(int(max_iter), 0) + 1) if history else None
         _check(h2b_cg_solve(self.handle, _vp(b.data_ptr()), _vp(x.data_ptr()), ctypes.byref(p), ctypes.byref(r),
@@ -347,6 +369,17 @@ def dtn_rhs(K, u, stream=None):
     b = torch.zeros(K.mesh.nt, dtype=torch.float64, device=u.device)
     K.mass_matvec(u, b, 0.5, stream=stream)
     K.matvec(u, b, stream=stream)
+    return b
+
+
+def ntd_rhs(K, t, stream=None):
+    """Right-hand side (M^T/2 - K^T) t of the Neumann-to-Dirichlet system
+    W u = (M^T/2 - K^T) t for the Neumann coefficients t (one per triangle)
+    and the double-layer operator K: two library calls."""
+    import torch
+    b = torch.zeros(K.mesh.nv, dtype=torch.float64, device=t.device)
+    K.mass_matvec(t, b, 0.5, trans=True, stream=stream)
+    K.matvec(t, b, alpha=-1.0, trans=True, stream=stream)
     return b
 
 

@@ -313,6 +313,15 @@ void h2b_cg_params_default(h2b_cg_params *p)
     p->check_every = 8;
     p->use_graph = 1;
     p->zero_guess = 1;
+    p->form = H2B_FORM_PRODUCT;
+}
+
+h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, double *y, void *hip_stream)
+{
+    return guarded([&] {
+        need(G, "G");
+        h2b::hypersingular_matvec(*G->op, alpha, x, y, static_cast<hipStream_t>(hip_stream));
+    });
 }
 
 h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, double *y, void *hip_stream)

@@ -1,6 +1,10 @@
-// Dirichlet-to-Neumann solve: the mixed mass matrix of Section 1 and the
-// conjugate gradient method on the H^2 product (eq. (matrix_dtn), solved by a
-// Krylov method in the experiments of Section 5).
+// Dirichlet-to-Neumann and Neumann-to-Dirichlet solves: the mixed mass matrix
+// of Section 1, the hypersingular matrix W through its representation by the
+// single-layer operator (W = sum_d C_d^T G C_d, C_d the d-th component of the
+// surface curls of the hat functions, constant on each flat triangle), and
+// the conjugate gradient method on the H^2 product of G or on W (eqs.
+// (matrix_dtn), (matrix_ntd), solved by a Krylov method in the experiments
+// of Section 5).
 //
 // Every scalar of the iteration (rho, alpha, beta, the count and the stop
 // flag) lives in device memory, so the host only queues work: one iteration
@@ -34,6 +38,7 @@ struct CgState {
     int status;      // 0 running, else h2b_cg_status
     int max_iter;
     int pad;
+    double shift;    // hypersingular form: coefficient of w1 removed from b, then of 1 removed from x
 };
 
 __device__ inline double wave_total(double v)
@@ -66,14 +71,14 @@ __device__ inline double parts_total(const double *part, int nb, double *lds)
 
 __device__ inline double rel_norm(double rr, double bb) { return sqrt(bb > 0.0 ? rr / bb : rr); }
 
-// part[g] = sum of a_i c_i over the slice of workgroup g.
+// part[g] = sum of a_i c_i (c = NULL: of a_i) over the slice of workgroup g.
 __global__ __launch_bounds__(KT) void k_dot_part(const double *__restrict__ a, const double *__restrict__ c,
                                                  int64_t n, double *__restrict__ part)
 {
     __shared__ double lds[KT / 64];
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
-        acc += a[i] * c[i];
+        acc += c ? a[i] * c[i] : a[i];
     const double s = group_total(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -101,6 +106,25 @@ __global__ __launch_bounds__(KT) void k_cg_start(const double *__restrict__ pb, 
         S->status = rr <= tol * tol * bb ? H2B_CG_CONVERGED : max_iter == 0 ? H2B_CG_MAXITER : 0;
         hist[0] = rel_norm(rr, bb);
     }
+}
+
+// S->shift = (sum of pnum) / (sum of pden).
+__global__ __launch_bounds__(KT) void k_ratio(const double *__restrict__ pnum, const double *__restrict__ pden,
+                                              int nb, CgState *S)
+{
+    __shared__ double lds[KT / 64];
+    const double num = parts_total(pnum, nb, lds);
+    const double den = parts_total(pden, nb, lds);
+    if (threadIdx.x == 0) S->shift = den != 0.0 ? num / den : 0.0;
+}
+
+// y = a - S->shift * w (w = NULL: the vector of ones).
+__global__ __launch_bounds__(KT) void k_sub_shift(const double *a, const double *__restrict__ w, int64_t n,
+                                                  const CgState *S, double *y)
+{
+    const double c = S->shift;
+    for (int64_t i = blockIdx.x * (int64_t)KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT)
+        y[i] = a[i] - c * (w ? w[i] : 1.0);
 }
 
 // alpha = rho / p^T q (0 once stopped; breakdown when p^T q is not positive).
@@ -205,6 +229,67 @@ __global__ __launch_bounds__(KT) void k_mass_t(GeoDev g, int64_t nv, double alph
     }
 }
 
+// w1_j = int phi_j = sum over the triangles t around vertex j of |t| / 3.
+__global__ __launch_bounds__(KT) void k_p1_integrals(GeoDev g, int64_t nv, double *__restrict__ w1)
+{
+    for (int64_t j = blockIdx.x * (int64_t)KT + threadIdx.x; j < nv; j += (int64_t)gridDim.x * KT) {
+        double s = 0.0;
+        for (int64_t e = g.vt_ptr[j]; e < g.vt_ptr[j + 1]; ++e) s += tri_area(g, g.vt_idx[e]) / 3.0;
+        w1[j] = s;
+    }
+}
+
+// Surface curl of the hat function of corner j on triangle t: with the
+// corners (a, b, c) counter-clockwise, curl phi_a = (x_b - x_c) / (2|t|) and
+// cyclically (n x grad phi_a, n the outward normal).
+__device__ inline void corner_curl(const GeoDev &g, int32_t nxt, int32_t prv, double inv2a, double &cx, double &cy,
+                                   double &cz)
+{
+    cx = (g.vx[nxt] - g.vx[prv]) * inv2a;
+    cy = (g.vy[nxt] - g.vy[prv]) * inv2a;
+    cz = (g.vz[nxt] - g.vz[prv]) * inv2a;
+}
+
+// c[t + d nt] = (C_d x)_t = sum over the corners j of t of x_j (curl phi_j)_d.
+__global__ __launch_bounds__(KT) void k_curl(GeoDev g, int64_t nt, const double *__restrict__ x,
+                                             double *__restrict__ c)
+{
+    for (int64_t t = blockIdx.x * (int64_t)KT + threadIdx.x; t < nt; t += (int64_t)gridDim.x * KT) {
+        const int32_t a = g.t0[t], b = g.t1[t], d = g.t2[t];
+        const double inv2a = 1.0 / (2.0 * tri_area(g, t));
+        double sx = 0.0, sy = 0.0, sz = 0.0, cx, cy, cz;
+        corner_curl(g, b, d, inv2a, cx, cy, cz);
+        sx += x[a] * cx, sy += x[a] * cy, sz += x[a] * cz;
+        corner_curl(g, d, a, inv2a, cx, cy, cz);
+        sx += x[b] * cx, sy += x[b] * cy, sz += x[b] * cz;
+        corner_curl(g, a, b, inv2a, cx, cy, cz);
+        sx += x[d] * cx, sy += x[d] * cy, sz += x[d] * cz;
+        c[t] = sx;
+        c[t + nt] = sy;
+        c[t + 2 * nt] = sz;
+    }
+}
+
+// y_j += alpha sum over the triangles t around vertex j of
+// sum_d (curl phi_j on t)_d gc[t + d nt]  (the transpose of k_curl).
+__global__ __launch_bounds__(KT) void k_curl_t(GeoDev g, int64_t nv, int64_t nt, const double *__restrict__ gc,
+                                               double alpha, double *__restrict__ y)
+{
+    for (int64_t j = blockIdx.x * (int64_t)KT + threadIdx.x; j < nv; j += (int64_t)gridDim.x * KT) {
+        double s = 0.0;
+        for (int64_t e = g.vt_ptr[j]; e < g.vt_ptr[j + 1]; ++e) {
+            const int32_t t = g.vt_idx[e];
+            const int32_t a = g.t0[t], b = g.t1[t], d = g.t2[t];
+            const int32_t nxt = j == a ? b : j == b ? d : a;
+            const int32_t prv = j == a ? d : j == b ? a : b;
+            double cx, cy, cz;
+            corner_curl(g, nxt, prv, 1.0 / (2.0 * tri_area(g, t)), cx, cy, cz);
+            s += cx * gc[t] + cy * gc[t + nt] + cz * gc[t + 2 * nt];
+        }
+        y[j] += alpha * s;
+    }
+}
+
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(KMAXB, (n + KT * 4 - 1) / (KT * 4))); }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb)
@@ -215,7 +300,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb)
 
 // Owner of the resources of one solve.
 struct CgRun {
-    DevMem r, p, q, part, part2, state, hist;
+    DevMem r, p, q, part, part2, state, hist, w1, bp;
     CgState *host = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -245,18 +330,65 @@ void mass_matvec(Op &op, int trans, double alpha, const double *x, double *y, hi
     hip_check(hipGetLastError(), "mass launch");
 }
 
+static void check_single_layer(const Op &G)
+{
+    if (G.kernel != H2B_SLP || G.nrows != G.ncols)
+        fail(H2B_EINVAL, "the hypersingular product needs the single-layer operator G");
+}
+
+void prepare_hypersingular(Op &G)
+{
+    check_single_layer(G);
+    const size_t bytes = sizeof(double) * 3 * (size_t)G.nrows;
+    if (G.hs_c.bytes < bytes) {
+        G.hs_c.alloc(bytes);
+        G.hs_g.alloc(bytes);
+    }
+    prepare_product(G, 3);
+}
+
+void hypersingular_matvec(Op &G, double alpha, const double *x, double *y, hipStream_t st)
+{
+    check_single_layer(G);
+    const Mesh &M = *G.blocks->rows->mesh;
+    const int64_t nt = M.nt, nv = M.nv;
+    if (!x || !y) fail(H2B_EINVAL, "x and y must not be NULL");
+    if (overlaps(x, sizeof(double) * nv, y, sizeof(double) * nv)) fail(H2B_EINVAL, "x and y overlap");
+    prepare_hypersingular(G);
+    double *c = G.hs_c.as<double>(), *gc = G.hs_g.as<double>();
+    hipLaunchKernelGGL(k_curl, dim3(grid_for(nt)), dim3(KT), 0, st, G.geo, nt, x, c);
+    hip_check(hipGetLastError(), "curl launch");
+    launch_fill_zero<double>(gc, 3 * nt, st);
+    matvec(G, 0, 1.0, c, nt, gc, nt, 3, st);
+    hipLaunchKernelGGL(k_curl_t, dim3(grid_for(nv)), dim3(KT), 0, st, G.geo, nv, nt, gc, alpha, y);
+    hip_check(hipGetLastError(), "curl transpose launch");
+}
+
 void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_cg_result &res, double *history,
               hipStream_t st)
 {
     const auto t0 = std::chrono::steady_clock::now();
-    if (A.nrows != A.ncols) fail(H2B_EINVAL, "conjugate gradients need a square operator");
-    const int64_t n = A.nrows;
+    const bool hyp = prm.form == H2B_FORM_HYPERSINGULAR;
+    if (prm.form != H2B_FORM_PRODUCT && !hyp) fail(H2B_EINVAL, "unknown operator form");
+    if (hyp) check_single_layer(A);
+    if (!hyp && A.nrows != A.ncols) fail(H2B_EINVAL, "conjugate gradients need a square operator");
+    const int64_t n = hyp ? A.blocks->rows->mesh->nv : A.nrows;
+    // q += A p (or W p)
+    auto apply = [&](const double *in, double *out, double alpha, hipStream_t s) {
+        if (hyp)
+            hypersingular_matvec(A, alpha, in, out, s);
+        else
+            matvec(A, 0, alpha, in, n, out, n, 1, s);
+    };
     if (!b || !x) fail(H2B_EINVAL, "b and x must not be NULL");
     if (overlaps(b, sizeof(double) * n, x, sizeof(double) * n)) fail(H2B_EINVAL, "b and x overlap");
     if (!(prm.tol >= 0.0) || !std::isfinite(prm.tol)) fail(H2B_EINVAL, "tol must be finite and >= 0");
     if (prm.max_iter < 0) fail(H2B_EINVAL, "max_iter must be >= 0");
     if (prm.check_every < 1) fail(H2B_EINVAL, "check_every must be >= 1");
-    prepare_product(A, 1);
+    if (hyp)
+        prepare_hypersingular(A);
+    else
+        prepare_product(A, 1);
 
     CgRun w;
     const int nb = grid_for(n);
@@ -273,10 +405,25 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     double *part = w.part.as<double>(), *part2 = w.part2.as<double>(), *hist = w.hist.as<double>();
     CgState *S = w.state.as<CgState>();
 
+    if (hyp) {
+        // W annihilates constants and b is orthogonal to them only up to
+        // quadrature error: solve W x = b - c w1 with c = 1^T b / 1^T w1
+        // (w1_j = int phi_j), the consistent system whose solution with
+        // int u_h = w1^T x = 0 is that of the system bordered by w1
+        w.w1.alloc(sizeof(double) * n);
+        w.bp.alloc(sizeof(double) * n);
+        hipLaunchKernelGGL(k_p1_integrals, dim3(nb), dim3(KT), 0, st, A.geo, n, w.w1.as<double>());
+        hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, b, nullptr, n, part);
+        hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, w.w1.as<double>(), nullptr, n, part2);
+        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(KT), 0, st, part, part2, nb, S);
+        hipLaunchKernelGGL(k_sub_shift, dim3(nb), dim3(KT), 0, st, b, w.w1.as<double>(), n, S, w.bp.as<double>());
+        hip_check(hipGetLastError(), "cg projection");
+        b = w.bp.as<double>();
+    }
     // r0 = b - A x0, p0 = r0, q = 0
     if (prm.zero_guess) launch_fill_zero<double>(x, n, st);
     hipLaunchKernelGGL(k_copy, dim3(nb), dim3(KT), 0, st, b, r, n);
-    if (!prm.zero_guess) matvec(A, 0, -1.0, x, n, r, n, 1, st);
+    if (!prm.zero_guess) apply(x, r, -1.0, st);
     hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, b, b, n, part);
     hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, r, r, n, part2);
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(KT), 0, st, part, part2, nb, prm.tol, prm.max_iter, S, hist);
@@ -310,7 +457,7 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         hip_check(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal), "begin capture");
         try {
             for (int k = 0; k < per; ++k) {
-                matvec(A, 0, 1.0, p, n, q, n, 1, w.cap);
+                apply(p, q, 1.0, w.cap);
                 update(w.cap);
             }
         } catch (...) {
@@ -330,12 +477,21 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
             hip_check(hipGraphLaunch(w.exec, st), "graph launch");
         else
             for (int k = 0; k < per; ++k) {
-                matvec(A, 0, 1.0, p, n, q, n, 1, st);
+                apply(p, q, 1.0, st);
                 update(st);
             }
         cur = read_state();
     }
     if (cur.status == 0) fail(H2B_EDEVICE, "conjugate gradients did not reach a stop state");
+    if (hyp) {
+        // the representative with int u_h = w1^T x = 0
+        hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, w.w1.as<double>(), x, n, part);
+        hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, w.w1.as<double>(), nullptr, n, part2);
+        hipLaunchKernelGGL(k_ratio, dim3(1), dim3(KT), 0, st, part, part2, nb, S);
+        hipLaunchKernelGGL(k_sub_shift, dim3(nb), dim3(KT), 0, st, x, nullptr, n, S, x);
+        hip_check(hipGetLastError(), "cg normalisation");
+        hip_check(hipStreamSynchronize(st), "cg normalisation");
+    }
     if (history)
         hip_check(hipMemcpy(history, hist, sizeof(double) * ((size_t)cur.iter + 1), hipMemcpyDeviceToHost),
                   "history read");

@@ -94,6 +94,7 @@ struct Op {
     hipEvent_t fork = nullptr, join = nullptr;
     bool overlap = true;                    // false: the nearfield stays on the caller's stream
     DevMem gxp, gyp, gax, gay;              // shape-gradient work vectors
+    DevMem hs_c, hs_g;                      // hypersingular product: curls and G times curls (3 nt each)
     int mrhs_rb = 0;                        // block width the block vectors are sized for
     int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)
     bool timing = false;
@@ -156,7 +157,11 @@ void slp_shape_grad(Op &op, const double *x, const double *y, double *gx, double
 void op_stats(const Op &op, h2b_op_stats &s);
 // y += alpha M x (trans = 0) or alpha M^T x (trans = 1), M the mixed mass matrix.
 void mass_matvec(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st);
-// Conjugate gradients for A x = b with the H^2 product of A.
+// y += alpha W x, W = sum_d C_d^T G C_d the hypersingular matrix from G.
+void hypersingular_matvec(Op &G, double alpha, const double *x, double *y, hipStream_t st);
+// Allocates what hypersingular_matvec needs (before a capture).
+void prepare_hypersingular(Op &G);
+// Conjugate gradients for A x = b with the H^2 product of A (or W x = b).
 void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_cg_result &res, double *history,
               hipStream_t st);
 

@@ -274,3 +274,108 @@ def test_cg_stops_and_rejects():
         setattr(q, field, bad)
         assert h.h2b_cg_solve(G.handle, bp, xp, ctypes.byref(q), ctypes.byref(res), None, s0) == h.H2B_EINVAL
     assert h.h2b_mass_matvec(G.handle, 0, 1.0, bp, None, s0) == h.H2B_EINVAL
+
+
+# ------------------------------------------------ hypersingular, Neumann-to-Dirichlet
+
+_ntd_cache = {}
+
+
+def _oracle_ntd(s, q=4):
+    if s not in _ntd_cache:
+        v, t = synth.octa_sphere(s)
+        G, K, M = _oracle_dtn(s, q)
+        _ntd_cache[s] = (krylov.hypersingular_from_slp(G, krylov.curl_matrices(v, t)), K, M)
+    return _ntd_cache[s]
+
+
+def test_hypersingular_product_matches_oracle():
+    """W x = sum_d C_d^T G C_d x with the far field disabled equals the
+    oracle's dense W (from its dense G and curl matrices) to rounding; with
+    the order-4 far field it equals the same form of the oracle's dense H^2
+    matrix of G."""
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    G = h.Operator(v, t, kernel="slp", leaf=32, q_near=4, far_disabled=True)
+    W, _, _ = _oracle_ntd(8)
+    x = synth.random_vector(len(v), 61)
+    y0 = synth.random_vector(len(v), 62)
+    Y = _dev(y0)
+    G.hypersingular_matvec(_dev(x), Y, alpha=0.6)
+    assert _maxrel(_host(Y), y0 + 0.6 * (W @ x)) <= 1e-10
+    v, t = synth.octa_sphere(16)
+    Gd, _, _ = _oracle_dtn(16)
+    Gh, _ = h2.h2_dense(v, t, "slp", 32, 4, near_matrix=Gd)
+    Wh = krylov.hypersingular_from_slp(Gh, krylov.curl_matrices(v, t))
+    G = h.Operator(v, t, kernel="slp", leaf=32, order_m=4, q_near=4)
+    x = synth.random_vector(len(v), 63)
+    Y = _torch().zeros(len(v), dtype=_torch().float64, device="cuda")
+    G.hypersingular_matvec(_dev(x), Y)
+    assert _maxrel(_host(Y), Wh @ x) <= 1e-10
+
+
+def test_ntd_right_hand_side_matches_oracle():
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    K = h.Operator(v, t, kernel="dlp", leaf=32, q_near=4, far_disabled=True)
+    _, Kd, M = _oracle_ntd(8)
+    for name, (_, grad) in krylov.TEST_FUNCTIONS.items():
+        tn = krylov.neumann_projection(v, t, grad)
+        b = _host(h.ntd_rhs(K, _dev(tn)))
+        assert _maxrel(b, krylov.ntd_rhs(Kd, M, tn)) <= 1e-11, name
+
+
+def test_ntd_cg_matches_oracle_direct_solve():
+    """Far field disabled: CG on W (to 1e-12, from zero, on the right-hand
+    side made consistent along w1 = int phi_j) gives the oracle's bordered
+    direct solve of eq. (matrix_ntd), both with int u_h = 0 (bound 1e-8);
+    graph replay and eager queueing give the same bits."""
+    h = _lib()
+    torch = _torch()
+    v, t = synth.octa_sphere(8)
+    G = h.Operator(v, t, kernel="slp", leaf=32, q_near=4, far_disabled=True)
+    K = h.Operator(v, t, kernel="dlp", leaf=32, q_near=4, far_disabled=True)
+    W, Kd, M = _oracle_ntd(8)
+    tn = krylov.neumann_projection(v, t, krylov.grad_u2)
+    b = h.ntd_rhs(K, _dev(tn))
+    xs = []
+    for graph in (True, False):
+        x = torch.zeros_like(b)
+        r = G.cg(b, x, tol=1e-12, max_iter=1000, form="hypersingular", use_graph=graph)
+        assert r["status"] == "converged", r
+        xs.append(_host(x))
+    assert np.array_equal(xs[0], xs[1])
+    uo = krylov.ntd_solve(W, Kd, M, tn)
+    w1 = M.sum(axis=0)
+    assert abs(w1 @ xs[0]) <= 1e-12 * (w1 @ np.abs(xs[0]))
+    assert np.linalg.norm(xs[0] - uo) <= 1e-8 * np.linalg.norm(uo)
+
+
+def test_ntd_paper_functions_converge_second_order():
+    """Section 5 (L2 error of the Neumann-to-Dirichlet problem): the Dirichlet
+    data of u1, u2, u3 from eq. (matrix_ntd), with the P0 projections of
+    their Neumann data and CG to 1e-10 on the H^2 form of W, converge at
+    O(h^2) from s = 8 to 64 with the interpolation order rising with the
+    mesh as for the Dirichlet-to-Neumann problem."""
+    h = _lib()
+    torch = _torch()
+    errs = {name: [] for name in krylov.TEST_FUNCTIONS}
+    for s, m in ((8, 4), (16, 4), (32, 5), (64, 6)):
+        v, t = synth.octa_sphere(s)
+        print("ntd s=%d m=%d" % (s, m), flush=True)
+        rc = 1e-6 if m == 4 else 0.0
+        G = h.Operator(v, t, kernel="slp", leaf=32, order_m=m, q_near=4, recompress_tol=rc)
+        K = h.Operator(v, t, kernel="dlp", leaf=32, order_m=m, q_near=4, recompress_tol=rc)
+        for name, (u, grad) in krylov.TEST_FUNCTIONS.items():
+            b = h.ntd_rhs(K, _dev(krylov.neumann_projection(v, t, grad)))
+            x = torch.zeros_like(b)
+            r = G.cg(b, x, tol=1e-10, max_iter=3000, form="hypersingular")
+            assert r["status"] == "converged", (s, name, r)
+            e = krylov.dirichlet_l2_error(v, t, _host(x), u)
+            errs[name].append(e)
+    print(errs)
+    for name, e in errs.items():
+        assert all(e[i] > e[i + 1] for i in range(3)), (name, e)
+        for i in (1, 2):
+            rate = math.log2(e[i] / e[i + 1])
+            assert 1.6 <= rate <= 2.6, (name, e, rate)
