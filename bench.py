@@ -282,6 +282,48 @@ def dtn_solve(torch, h2b, ops, verts, tris, suffixes, ms_gx):
     return res
 
 
+def ntd_solve(torch, h2b, ops, verts, tris):
+    """Neumann-to-Dirichlet solve W u = (M^T/2 - K^T) t on the benchmark mesh,
+    W = sum_d C_d^T G C_d from the FP64 G, t the exact normal derivative of
+    u1 = x1^2 - x3^2 at the triangle centroids; CG to 1e-8 from u = 0."""
+    G, K = ops["G"], ops["K"]
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    n = cr / np.linalg.norm(cr, axis=1)[:, None]
+    cen = (a + b + c) / 3.0
+    tn = torch.tensor(2.0 * cen[:, 0] * n[:, 0] - 2.0 * cen[:, 2] * n[:, 2], dtype=torch.float64, device="cuda")
+    rhs = h2b.ntd_rhs(K, tn)
+    x = torch.zeros_like(rhs)
+    y = torch.zeros_like(rhs)
+    G.hypersingular_matvec(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        G.hypersingular_matvec(rhs, y)
+    torch.cuda.synchronize()
+    ms_w = (time.perf_counter() - t0) * 1e3 / 5
+    r = G.cg(rhs, x, tol=1e-8, max_iter=3000, form="hypersingular")
+    u = x.cpu().numpy()
+    ex = verts[:, 0] ** 2 - verts[:, 2] ** 2
+    # relative nodal error after matching the zero-mean representative
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    w1 = np.zeros(len(verts))
+    for k in range(3):
+        np.add.at(w1, tris[:, k], area / 3.0)
+    ex = ex - (w1 @ ex) / w1.sum()
+    it = max(r["iterations"], 1)
+    d = {"problem": "W u = (M^T/2 - K^T) t, t = d(x1^2 - x3^2)/dn at the centroids, CG tol 1e-8 from u = 0, "
+                    "W from the FP64 G",
+         "iterations": r["iterations"], "status": r["status"], "rel_residual": r["rel_residual"],
+         "solve_ms": round(r["solve_ms"], 2), "ms_per_iteration": round(r["solve_ms"] / it, 4),
+         "ms_hypersingular_product": round(ms_w, 4),
+         "nodal_rel_err_vs_u1": float(np.max(np.abs(u - ex)) / np.max(np.abs(ex)))}
+    log("NtD solve: %d iterations, %.1f ms (%.3f ms per iteration; W x alone %.3f ms), residual %.2e, "
+        "nodal error %.3e" % (r["iterations"], r["solve_ms"], r["solve_ms"] / it, ms_w, r["rel_residual"],
+                              d["nodal_rel_err_vs_u1"]))
+    return d
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +338,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
-    ap.add_argument("--no-solve", action="store_true", help="skip the Dirichlet-to-Neumann CG solve")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the Dirichlet-to-Neumann and Neumann-to-Dirichlet CG solves")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 2 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -501,6 +544,7 @@ def main():
         out["dtn_solve"] = dtn_solve(torch, h2b, ops, verts, tris, ("", "32") if not args.no_mixed else ("",),
                                      {"": detail["G"]["ms_Ax"],
                                       "32": detail["G32"]["ms_Ax"] if not args.no_mixed else None})
+        out["ntd_solve"] = ntd_solve(torch, h2b, ops, verts, tris)
 
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))

@@ -322,8 +322,7 @@ h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, 
  * counter-clockwise: curl phi_a = (x_b - x_c) / (2 |tau|), cyclically).
  * y += alpha W x with x, y device arrays of nv doubles (vertex order).  G is
  * the H^2 single-layer operator of the mesh (any precision settings); one
- * call is two small curl kernels around one product of G with three
- * right-hand sides.  The first call allocates 6 nt doubles of work vectors
+ * call is two small curl kernels around three products of G.  The first call allocates 6 nt doubles of work vectors
  * on the operator.  W annihilates constants.  Runs asynchronously on
  * hip_stream.  Errors: H2B_EINVAL if G is not the single-layer operator, for
  * NULL or overlapping x and y. */
