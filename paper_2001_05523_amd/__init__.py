@@ -40,7 +40,7 @@ _P = ctypes.POINTER
 class h2b_params(ctypes.Structure):
     _fields_ = [("order_m", ctypes.c_int), ("q_near", ctypes.c_int),
                 ("recompress_tol", ctypes.c_double), ("farfield_dtype", ctypes.c_int),
-                ("transposed_copy", ctypes.c_int), ("symmetric_near", ctypes.c_int)]
+                ("transposed_copy", ctypes.c_int), ("symmetric_near", ctypes.c_int), ("gca_tol", ctypes.c_double)]
 
 
 class h2b_op_stats(ctypes.Structure):
@@ -219,7 +219,7 @@ class Operator:
 
     def __init__(self, verts=None, tris=None, kernel="slp", leaf=32, order_m=4, q_near=4,
                  eta=1.0, far_disabled=False, recompress_tol=0.0, farfield_dtype="f64",
-                 transposed_copy=True, symmetric_near=True, stream=None, mesh=None):
+                 transposed_copy=True, symmetric_near=True, gca_tol=0.0, stream=None, mesh=None):
         self.mesh = mesh if mesh is not None else Mesh(verts, tris)
         self.kernel = H2B_SLP if kernel == "slp" else H2B_DLP
         self.rows = Tree(self.mesh, H2B_P0, leaf)
@@ -227,7 +227,7 @@ class Operator:
         self.blocks = Blocks(self.rows, self.cols, eta, far_disabled)
         p = default_params(order_m=order_m, q_near=q_near, recompress_tol=recompress_tol,
                            farfield_dtype=_DTYPES[farfield_dtype], transposed_copy=int(bool(transposed_copy)),
-                           symmetric_near=int(bool(symmetric_near)))
+                           symmetric_near=int(bool(symmetric_near)), gca_tol=float(gca_tol))
         h = _vp()
         _check(h2b_assemble(self.blocks.handle, self.kernel, ctypes.byref(p), _stream_ptr(stream),
                             ctypes.byref(h)))

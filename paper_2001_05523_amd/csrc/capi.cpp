@@ -182,6 +182,7 @@ void h2b_params_default(h2b_params *p)
     p->farfield_dtype = H2B_F64;
     p->transposed_copy = 1;
     p->symmetric_near = 1;
+    p->gca_tol = 0.0;
 }
 
 h2b_status h2b_assemble(h2b_blocks blocks, h2b_kernel kernel, const h2b_params *params,

@@ -1,0 +1,294 @@
+// Green cross approximation (GCA, Section 4) of the single-layer matrix G:
+// nested cluster bases by "algebraic interpolation" and couplings made of
+// matrix entries, G|_{t x s} ~ V_t G|_{t_hat x s_hat} V_s^T.
+//
+// For every cluster t, bottom-up:
+//   1. omega_t = B_t widened by delta_t (the largest side of B_t) on every
+//      side, so that dist(boundary of omega_t, B_t) = delta_t (Section 5);
+//   2. Green's representation formula on omega_t discretised by an m x m
+//      Gauss rule on each face: L = [A C], a_{i nu} = w^{1/2} int psi_i
+//      g(x, z_nu), c_{i nu} = w^{1/2} int psi_i dg/dn_z(x, z_nu), for the
+//      rows i of t (leaves) or of t_hat_1 followed by t_hat_2 (parents);
+//   3. cross approximation of L with full pivoting, stopped when the largest
+//      remaining entry is at most eps times the first pivot: row pivots tau,
+//      column pivots sigma;
+//   4. V = L|_{rows x sigma} (L|_{tau x sigma})^{-1}: the leaf basis V_t, or
+//      for a parent the stacked transfer matrices [E_1; E_2]; t_hat = rows[tau].
+// The host builds the bases (clusters of one level in parallel); the GPU
+// evaluates the coupling entries G|_{t_hat x s_hat} with the nearfield
+// quadrature kernel over panels whose rows and columns are pivot triangles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "linalg.hpp"
+#include "op.hpp"
+
+namespace h2b {
+
+namespace {
+
+constexpr double FOUR_PI = 12.566370614359172953850573533118;
+
+struct FaceRule {
+    int k = 0;
+    std::vector<double> z, n, sw;  // points (3k), outward normals (3k), square roots of the weights
+};
+
+// m x m Gauss points on each face of [lo, hi]: axis, then the low side
+// before the high side, then the two other axes in increasing order.
+FaceRule face_rule(const double *lo, const double *hi, int m, const std::vector<double> &t,
+                   const std::vector<double> &w)
+{
+    FaceRule F;
+    F.k = 6 * m * m;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+        for (int side = 0; side < 2; ++side)
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) {
+                    double z[3], n[3] = {0.0, 0.0, 0.0};
+                    z[ax] = side ? hi[ax] : lo[ax];
+                    z[o1] = lo[o1] + t[i] * (hi[o1] - lo[o1]);
+                    z[o2] = lo[o2] + t[j] * (hi[o2] - lo[o2]);
+                    n[ax] = side ? 1.0 : -1.0;
+                    for (int d = 0; d < 3; ++d) {
+                        F.z.push_back(z[d]);
+                        F.n.push_back(n[d]);
+                    }
+                    F.sw.push_back(std::sqrt(w[i] * w[j] * (hi[o1] - lo[o1]) * (hi[o2] - lo[o2])));
+                }
+    }
+    return F;
+}
+
+// L = [A C] (rows x 2k, row-major) with the collapsed q x q rule on each triangle.
+void green_matrix(const Mesh &M, const std::vector<int32_t> &rows, const FaceRule &F, const std::vector<double> &tq,
+                  const std::vector<double> &wq, std::vector<double> &L)
+{
+    const int k = F.k, q = (int)tq.size();
+    L.assign(rows.size() * 2 * (size_t)k, 0.0);
+    for (size_t r = 0; r < rows.size(); ++r) {
+        const int i = rows[r];
+        const int a = M.t0[i], b = M.t1[i], c = M.t2[i];
+        const double P0[3] = {M.vx[a], M.vy[a], M.vz[a]}, P1[3] = {M.vx[b], M.vy[b], M.vz[b]},
+                     P2[3] = {M.vx[c], M.vy[c], M.vz[c]};
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) e1[d] = P1[d] - P0[d], e2[d] = P2[d] - P1[d];
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                     cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double jac = std::sqrt(cx * cx + cy * cy + cz * cz);
+        double *row = &L[r * 2 * (size_t)k];
+        for (int qa = 0; qa < q; ++qa)
+            for (int qb = 0; qb < q; ++qb) {
+                const double u1 = tq[qa], u2 = tq[qa] * tq[qb], wt = wq[qa] * wq[qb] * tq[qa] * jac;
+                double x[3];
+                for (int d = 0; d < 3; ++d) x[d] = P0[d] + u1 * e1[d] + u2 * e2[d];
+                for (int nu = 0; nu < k; ++nu) {
+                    const double dx = x[0] - F.z[3 * nu], dy = x[1] - F.z[3 * nu + 1], dz = x[2] - F.z[3 * nu + 2];
+                    const double r2 = dx * dx + dy * dy + dz * dz, rr = std::sqrt(r2);
+                    const double g = 1.0 / (FOUR_PI * rr);
+                    const double dn = (dx * F.n[3 * nu] + dy * F.n[3 * nu + 1] + dz * F.n[3 * nu + 2]) * g / r2;
+                    row[nu] += wt * g;
+                    row[k + nu] += wt * dn;
+                }
+            }
+        for (int nu = 0; nu < k; ++nu) {
+            row[nu] *= F.sw[nu];
+            row[k + nu] *= F.sw[nu];
+        }
+    }
+}
+
+// Cross approximation with full pivoting of R (nr x nc, row-major, consumed).
+void aca_full(int nr, int nc, std::vector<double> &R, double eps, std::vector<int> &tau, std::vector<int> &sigma)
+{
+    tau.clear();
+    sigma.clear();
+    double first = -1.0;
+    for (int step = 0; step < std::min(nr, nc); ++step) {
+        int bi = 0, bj = 0;
+        double best = -1.0;
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j) {
+                const double v = std::fabs(R[(size_t)i * nc + j]);
+                if (v > best) best = v, bi = i, bj = j;
+            }
+        if (first < 0.0) {
+            first = best;
+            if (first == 0.0) break;
+        } else if (best <= eps * first) {
+            break;
+        }
+        tau.push_back(bi);
+        sigma.push_back(bj);
+        const double piv = R[(size_t)bi * nc + bj];
+        std::vector<double> col(nr), row(R.begin() + (size_t)bi * nc, R.begin() + (size_t)(bi + 1) * nc);
+        for (int i = 0; i < nr; ++i) col[i] = R[(size_t)i * nc + bj] / piv;
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j) R[(size_t)i * nc + j] -= col[i] * row[j];
+    }
+}
+
+// X (nr x k) = B (nr x k) A^{-1}: Gaussian elimination with partial pivoting
+// on A^T X^T = B^T.
+void solve_right(int k, const std::vector<double> &A, int nr, const std::vector<double> &B, std::vector<double> &X)
+{
+    std::vector<double> T((size_t)k * k), Y((size_t)k * nr);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) T[(size_t)i * k + j] = A[(size_t)j * k + i];
+    for (int i = 0; i < k; ++i)
+        for (int r = 0; r < nr; ++r) Y[(size_t)i * nr + r] = B[(size_t)r * k + i];
+    for (int c = 0; c < k; ++c) {
+        int p = c;
+        for (int i = c + 1; i < k; ++i)
+            if (std::fabs(T[(size_t)i * k + c]) > std::fabs(T[(size_t)p * k + c])) p = i;
+        if (T[(size_t)p * k + c] == 0.0) fail(H2B_EDEVICE, "singular pivot block in the cross approximation");
+        if (p != c) {
+            for (int j = 0; j < k; ++j) std::swap(T[(size_t)c * k + j], T[(size_t)p * k + j]);
+            for (int r = 0; r < nr; ++r) std::swap(Y[(size_t)c * nr + r], Y[(size_t)p * nr + r]);
+        }
+        for (int i = c + 1; i < k; ++i) {
+            const double f = T[(size_t)i * k + c] / T[(size_t)c * k + c];
+            if (f == 0.0) continue;
+            for (int j = c; j < k; ++j) T[(size_t)i * k + j] -= f * T[(size_t)c * k + j];
+            for (int r = 0; r < nr; ++r) Y[(size_t)i * nr + r] -= f * Y[(size_t)c * nr + r];
+        }
+    }
+    for (int c = k - 1; c >= 0; --c) {
+        for (int j = c + 1; j < k; ++j) {
+            const double f = T[(size_t)c * k + j];
+            for (int r = 0; r < nr; ++r) Y[(size_t)c * nr + r] -= f * Y[(size_t)j * nr + r];
+        }
+        for (int r = 0; r < nr; ++r) Y[(size_t)c * nr + r] /= T[(size_t)c * k + c];
+    }
+    X.assign((size_t)nr * k, 0.0);
+    for (int r = 0; r < nr; ++r)
+        for (int i = 0; i < k; ++i) X[(size_t)r * k + i] = Y[(size_t)i * nr + r];
+}
+
+template <typename TO> __global__ void k_convert(const double *__restrict__ in, TO *__restrict__ out, int64_t n)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (TO)in[e];
+}
+
+}  // namespace
+
+GcaBases gca_bases(const Tree &T, int m, double eps)
+{
+    const Mesh &M = *T.mesh;
+    const int64_t nc = T.nclusters();
+    GcaBases G;
+    G.rank.assign(nc, 0);
+    G.hat.assign(nc, {});
+    G.V.assign(nc, {});
+    std::vector<double> t, w, tq, wq;
+    gauss_legendre_unit(m, t, w);
+    gauss_legendre_unit(m + 2, tq, wq);
+    for (int lev = T.nlevels - 1; lev >= 0; --lev) {
+        const std::vector<int32_t> &cl = T.by_level[lev];
+        parallel_for((int64_t)cl.size(), [&](int64_t idx) {
+            const int c = cl[idx];
+            std::vector<int32_t> rows;
+            if (T.nchild[c] == 0) {
+                for (int p = T.begin[c]; p < T.end[c]; ++p) rows.push_back(T.perm[p]);
+            } else {
+                for (int ch : {T.child0[c], T.child1[c]}) rows.insert(rows.end(), G.hat[ch].begin(), G.hat[ch].end());
+            }
+            const double *bx = &T.box[6 * (size_t)c];
+            double delta = 0.0;
+            for (int d = 0; d < 3; ++d) delta = std::max(delta, bx[3 + d] - bx[d]);
+            const double lo[3] = {bx[0] - delta, bx[1] - delta, bx[2] - delta};
+            const double hi[3] = {bx[3] + delta, bx[4] + delta, bx[5] + delta};
+            const FaceRule F = face_rule(lo, hi, m, t, w);
+            std::vector<double> L;
+            green_matrix(M, rows, F, tq, wq, L);
+            const int nr = (int)rows.size(), ncol = 2 * F.k;
+            std::vector<double> R = L;
+            std::vector<int> tau, sigma;
+            aca_full(nr, ncol, R, eps, tau, sigma);
+            const int kk = (int)tau.size();
+            std::vector<double> Ats((size_t)kk * kk), Ls((size_t)nr * kk);
+            for (int i = 0; i < kk; ++i)
+                for (int j = 0; j < kk; ++j) Ats[(size_t)i * kk + j] = L[(size_t)tau[i] * ncol + sigma[j]];
+            for (int r = 0; r < nr; ++r)
+                for (int j = 0; j < kk; ++j) Ls[(size_t)r * kk + j] = L[(size_t)r * ncol + sigma[j]];
+            if (kk > 0) solve_right(kk, Ats, nr, Ls, G.V[c]);
+            G.rank[c] = kk;
+            G.hat[c].resize(kk);
+            for (int i = 0; i < kk; ++i) G.hat[c][i] = rows[tau[i]];
+        });
+    }
+    return G;
+}
+
+void set_gca_values(Op &op, const GcaBases &G, hipStream_t st)
+{
+    Basis &B = *op.rowb;
+    const Tree &T = *B.tree;
+    const h2b_dtype dt = op.params.farfield_dtype;
+    // leaf panels hold V_t^T (k_t x |t|), transfer panels [E_1^T | E_2^T]
+    std::vector<double> leaf(std::max<int64_t>(B.leaf.total, 1)), tr(std::max<int64_t>(B.trans.total, 1));
+    for (int g = 0; g < B.leaf.ngroups(); ++g) {
+        const int c = B.leaf.group_tag[g], n = T.size(c), k = G.rank[c];
+        for (int nu = 0; nu < k; ++nu)
+            for (int i = 0; i < n; ++i) leaf[B.leaf.val_off[g] + (int64_t)nu * n + i] = G.V[c][(size_t)i * k + nu];
+    }
+    for (int g = 0; g < B.trans.ngroups(); ++g) {
+        const int c = B.trans.group_tag[g], k = G.rank[c];
+        const int n = G.rank[T.child0[c]] + G.rank[T.child1[c]];
+        for (int nu = 0; nu < k; ++nu)
+            for (int mu = 0; mu < n; ++mu) tr[B.trans.val_off[g] + (int64_t)nu * n + mu] = G.V[c][(size_t)mu * k + nu];
+    }
+    auto up = [&](const std::vector<double> &v, DevMem &mem) {
+        if (dt == H2B_F64) {
+            mem.alloc(v.size() * sizeof(double));
+            hip_check(hipMemcpyAsync(mem.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st),
+                      "upload");
+        } else {
+            std::vector<float> f(v.begin(), v.end());
+            mem.alloc(f.size() * sizeof(float));
+            hip_check(hipMemcpyAsync(mem.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st),
+                      "upload");
+        }
+        hip_check(hipStreamSynchronize(st), "upload");
+    };
+    up(leaf, B.leaf_vals);
+    up(tr, B.trans_vals);
+    transpose_basis_values(B, dt, st);
+
+    // couplings: entries G_{i j} for the pivot triangles i of t_hat, j of s_hat
+    std::vector<int32_t> hidx(std::max<int64_t>(B.hat_total, 1), 0);
+    for (int64_t c = 0; c < T.nclusters(); ++c)
+        for (int i = 0; i < G.rank[c]; ++i) hidx[B.hat_off[c] + i] = G.hat[c][i];
+    DevMem dh;
+    dh.alloc(sizeof(int32_t) * hidx.size());
+    hip_check(hipMemcpyAsync(dh.p, hidx.data(), sizeof(int32_t) * hidx.size(), hipMemcpyHostToDevice, st),
+              "upload");
+    const int64_t n = std::max<int64_t>(op.cpl.total, 1);
+    DevMem s64;
+    double *dst = nullptr;
+    if (dt == H2B_F64) {
+        op.cpl_vals.alloc(sizeof(double) * n);
+        dst = op.cpl_vals.as<double>();
+    } else {
+        s64.alloc(sizeof(double) * n);
+        dst = s64.as<double>();
+    }
+    launch_near_assemble(H2B_SLP, op.cpl, dh.as<int32_t>(), dh.as<int32_t>(), op.geo, make_quad(op.params.q_near), dst,
+                         st);
+    if (dt != H2B_F64) {
+        op.cpl_vals.alloc(coupling_size(dt) * n);
+        const int nb = (int)std::min<int64_t>((n + 255) / 256, 65536);
+        if (dt == H2B_F32)
+            hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(256), 0, st, dst, op.cpl_vals.as<float>(), n);
+        else
+            hipLaunchKernelGGL(k_convert<bf16_t>, dim3(nb), dim3(256), 0, st, dst, op.cpl_vals.as<bf16_t>(), n);
+        hip_check(hipGetLastError(), "convert launch");
+    }
+    hip_check(hipStreamSynchronize(st), "gca couplings");
+}
+
+}  // namespace h2b

@@ -69,7 +69,7 @@ void regroup_transposed(const ColPanels &cp, RowPanels &out)
 
 static int basis_quad_order(int m) { return (3 * m) / 2 + 1; }
 
-static QuadDev make_quad(int q)
+QuadDev make_quad(int q)
 {
     if (q < 1 || q > QMAX) fail(H2B_EINVAL, "quadrature order out of range");
     QuadDev Q{};
@@ -220,6 +220,11 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (kernel != H2B_SLP && kernel != H2B_DLP) fail(H2B_EINVAL, "unknown kernel");
     if (p.recompress_tol > 0.0 && p.order_m > 4)
         fail(H2B_ENOTSUP, "recompression supports order_m <= 4");
+    if (!(p.gca_tol >= 0.0) || !std::isfinite(p.gca_tol)) fail(H2B_EINVAL, "gca_tol must be finite and >= 0");
+    const bool gca = p.gca_tol > 0.0;
+    if (gca && p.recompress_tol > 0.0) fail(H2B_EINVAL, "choose either recompression or the Green cross approximation");
+    if (gca && (kernel != H2B_SLP || blocks->rows != blocks->cols))
+        fail(H2B_ENOTSUP, "the Green cross approximation is built for the single-layer matrix on one tree");
 
     auto op = std::make_unique<Op>();
     op->blocks = blocks;
@@ -266,8 +271,12 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (op->colb != op->rowb) upload_axes(C, m, op->colb->axes, st);
     std::vector<Basis *> bases{op->rowb.get()};
     if (op->colb != op->rowb) bases.push_back(op->colb.get());
+    // Green cross approximation: pivots and nested bases first (host), their
+    // ranks shape the basis and coupling panels
+    GcaBases gb;
+    if (gca) gb = gca_bases(R, m, p.gca_tol);
     for (Basis *B : bases) {
-        build_basis_structure(*B, std::vector<int>(B->tree->nclusters(), k), st);
+        build_basis_structure(*B, gca ? gb.rank : std::vector<int>(B->tree->nclusters(), k), st);
         B->leaf.upload(st);
         B->leaf_T.upload(st);
         B->trans.upload(st);
@@ -317,6 +326,9 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     // with recompression the interpolation operator is built in FP64 first
     const bool rc = p.recompress_tol > 0.0;
     const h2b_dtype adt = rc ? H2B_F64 : p.farfield_dtype;
+    if (gca) {
+        set_gca_values(*op, gb, st);
+    } else {
     op->cpl_vals.alloc(coupling_size(adt) * std::max<int64_t>(op->cpl.total, 1));
     for (Basis *B : bases) {
         if (adt == H2B_F64)
@@ -332,6 +344,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
         launch_coupling<float>(op->cpl, rax, cax, m, op->cpl_vals.as<float>(), st);
     else
         launch_coupling<bf16_t>(op->cpl, rax, cax, m, op->cpl_vals.as<bf16_t>(), st);
+    }
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
     if (p.transposed_copy) make_transposed_copies(*op, st);
@@ -856,9 +869,9 @@ namespace h2b {
 void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, hipStream_t st)
 {
     if (!vx || !vy || !vz) fail(H2B_EINVAL, "vertex arrays must not be NULL");
-    if (op.params.recompress_tol > 0.0)
-        fail(H2B_ENOTSUP, "geometry updates keep the interpolation bases frozen; recompressed operators "
-                          "are not supported");
+    if (op.params.recompress_tol > 0.0 || op.params.gca_tol > 0.0)
+        fail(H2B_ENOTSUP, "geometry updates keep the interpolation bases frozen; recompressed and "
+                          "cross-approximation operators are not supported");
     const Mesh &M = *op.rowb->tree->mesh;
     const int64_t nv = M.nv, nt = M.nt;
     std::vector<double> nx(nt), ny(nt), nz(nt);

@@ -110,6 +110,22 @@ inline size_t coupling_size(h2b_dtype dt)
     return dt == H2B_F64 ? sizeof(double) : dt == H2B_F32 ? sizeof(float) : sizeof(bf16_t);
 }
 
+QuadDev make_quad(int q);
+
+// Green cross approximation of G on one tree: per cluster the rank k_t, the
+// pivot triangles t_hat (original indices, pivot order) and V, the leaf basis
+// (|t| x k_t, position order) or the stacked transfers [E_1; E_2]
+// ((k_1 + k_2) x k_t), both row-major.
+struct GcaBases {
+    std::vector<int> rank;
+    std::vector<std::vector<int32_t>> hat;
+    std::vector<std::vector<double>> V;
+};
+GcaBases gca_bases(const Tree &T, int m, double eps);
+// Basis values (in the far-field dtype) and coupling entries G|_{t_hat x s_hat}
+// of an operator whose panels were built with the GCA ranks.
+void set_gca_values(Op &op, const GcaBases &G, hipStream_t st);
+
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
 void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st);
