@@ -24,6 +24,13 @@ Steps, in the order of Section 4:
 * G|_{t x s} ~ V_t G|_{t_hat x s_hat} V_s^T for the farfield blocks (the same
   construction on the column cluster; for G both trees are the same), the
   entries G|_{t_hat x s_hat} taken from the dense Galerkin matrix.
+* The double-layer matrix K "takes the appropriate derivatives" (Section 5):
+  its rows use the same V_t (x -> dg/dn_y(x, y) is harmonic in omega_t too);
+  its columns (hat functions phi_j on the vertices of a cluster s) apply
+  Green's formula in y on omega_s and differentiate it in n_y, so that
+  L_s = [B D] with b_{j nu} = w^{1/2} int phi_j(y) dg/dn_y(y, z_nu) dy and
+  d_{j nu} = w^{1/2} int phi_j(y) d^2 g/(dn_y dn_z)(y, z_nu) dy, and
+  K|_{t x s} ~ V_t K|_{t_hat x s_hat} W_s^T.
 
 The triangle integrals of L use the collapsed Gauss rule with m + 2 points
 per direction.
@@ -86,6 +93,35 @@ def green_matrix(verts, tris, rows, Z, W, N, q):
     return L
 
 
+def green_matrix_p1(verts, tris, adj, rows, Z, W, N, q):
+    """L_s = [B D] for the vertices `rows` (hat functions, normal derivatives
+    in y of Green's formula on the column box)."""
+    U, Wt = triangle_rule(q)
+    lam = np.stack([1.0 - U[:, 0], U[:, 0] - U[:, 1], U[:, 1]], axis=1)
+    k = len(Z)
+    L = np.zeros((len(rows), 2 * k))
+    sw = np.sqrt(W)
+    for r, j in enumerate(rows):
+        for tri_id in adj[j]:
+            tri = tris[tri_id]
+            corner = int(np.where(tri == j)[0][0])
+            P0, P1, P2 = verts[tri[0]], verts[tri[1]], verts[tri[2]]
+            X = P0[None, :] + U[:, :1] * (P1 - P0)[None, :] + U[:, 1:2] * (P2 - P1)[None, :]
+            cr = np.cross(P1 - P0, P2 - P1)
+            jac = np.linalg.norm(cr)
+            ny = cr / jac
+            D = X[:, None, :] - Z[None, :, :]            # y - z
+            R = np.linalg.norm(D, axis=2)
+            dny = D @ ny                                  # n_y . (y - z)
+            dnz = np.einsum("qkd,kd->qk", D, N)           # n_z . (y - z)
+            b = -dny / (FOUR_PI * R ** 3)                 # dg/dn_y(y, z)
+            d = (N @ ny)[None, :] / (FOUR_PI * R ** 3) - 3.0 * dny * dnz / (FOUR_PI * R ** 5)
+            wl = Wt * lam[:, corner] * jac
+            L[r, :k] += sw * (wl @ b)
+            L[r, k:] += sw * (wl @ d)
+    return L
+
+
 def aca_full(L, eps):
     """Cross approximation with full pivoting: returns the row and column
     pivot lists (positions in L) in the order chosen."""
@@ -108,12 +144,19 @@ def aca_full(L, eps):
     return tau, sigma
 
 
-def gca_bases(verts, tris, clusters, perm, m, eps, q=None):
-    """Bottom-up GCA: for every cluster the pivot triangles t_hat (original
-    indices) and, for leaves, V_t (|t| x k_t in the cluster's position order)
-    or, for parents, V_hat_t ((k_1 + k_2) x k_t)."""
+def gca_bases(verts, tris, clusters, perm, m, eps, q=None, space="P0"):
+    """Bottom-up GCA: for every cluster the pivot indices t_hat (original
+    triangle indices, or vertex indices for space 'P1') and, for leaves, V_t
+    (|t| x k_t in the cluster's position order) or, for parents, V_hat_t
+    ((k_1 + k_2) x k_t)."""
     q = m + 2 if q is None else q
     hat, V = {}, {}
+    adj = None
+    if space == "P1":
+        adj = [[] for _ in range(len(verts))]
+        for k, tri in enumerate(tris):
+            for v in tri:
+                adj[v].append(k)
     for c in sorted(clusters, key=lambda c: -c.level):
         if c.children:
             rows = np.concatenate([hat[ch.id] for ch in c.children]).astype(np.int64)
@@ -121,7 +164,10 @@ def gca_bases(verts, tris, clusters, perm, m, eps, q=None):
             rows = perm[c.begin:c.end]
         lo, hi = omega_box(c.lo, c.hi)
         Z, W, N = face_rule(lo, hi, m)
-        L = green_matrix(verts, tris, rows, Z, W, N, q)
+        if space == "P1":
+            L = green_matrix_p1(verts, tris, adj, rows, Z, W, N, q)
+        else:
+            L = green_matrix(verts, tris, rows, Z, W, N, q)
         tau, sigma = aca_full(L, eps)
         Ls = L[:, sigma]
         V[c.id] = np.linalg.solve(L[np.ix_(tau, sigma)].T, Ls.T).T
@@ -168,4 +214,34 @@ def gca_dense(verts, tris, leaf, m, eps, G, eta=1.0):
         ri, ci = perm[t.begin:t.end], perm[s.begin:s.end]
         A[np.ix_(ri, ci)] = full[t.id] @ G[np.ix_(hat[t.id], hat[s.id])] @ full[s.id].T
     info = dict(ranks={c.id: len(hat[c.id]) for c in clusters}, hat=hat, far=len(far), near=len(near))
+    return A, info
+
+
+def gca_dense_dlp(verts, tris, leaf, m, eps, K, eta=1.0):
+    """Dense matrix of the GCA H^2 approximation of K (triangle rows,
+    vertex columns; nearfield and pivot entries from the dense K)."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    cent = verts[tris].mean(axis=1)
+    rt, rperm, rcl = cluster_tree(cent, leaf)
+    support_boxes(rcl, verts, tris, "P0")
+    ct, cperm, ccl = cluster_tree(verts, leaf)
+    support_boxes(ccl, verts, tris, "P1")
+    far, near = block_tree(rt, ct, eta)
+    rhat, RV = gca_bases(verts, tris, rcl, rperm, m, eps)
+    chat, CV = gca_bases(verts, tris, ccl, cperm, m, eps, space="P1")
+    A = np.zeros((len(tris), len(verts)))
+    for t, s in near:
+        ri, ci = rperm[t.begin:t.end], cperm[s.begin:s.end]
+        A[np.ix_(ri, ci)] = K[np.ix_(ri, ci)]
+    rf, cf = {}, {}
+    for t, s in far:
+        if t.id not in rf:
+            rf[t.id] = full_basis(t, RV)
+        if s.id not in cf:
+            cf[s.id] = full_basis(s, CV)
+        ri, ci = rperm[t.begin:t.end], cperm[s.begin:s.end]
+        A[np.ix_(ri, ci)] = rf[t.id] @ K[np.ix_(rhat[t.id], chat[s.id])] @ cf[s.id].T
+    info = dict(row_ranks={c.id: len(rhat[c.id]) for c in rcl}, col_ranks={c.id: len(chat[c.id]) for c in ccl},
+                far=len(far), near=len(near))
     return A, info

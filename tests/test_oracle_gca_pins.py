@@ -98,3 +98,20 @@ def test_gca_converges_to_the_galerkin_matrix():
         errs.append(np.linalg.norm(A @ x - G @ x) / np.linalg.norm(G @ x))
     assert errs[0] > 100 * errs[1] and errs[1] > 100 * errs[2], errs
     assert errs[0] < 1e-2, errs
+
+
+def test_gca_double_layer_converges_to_the_galerkin_matrix():
+    """K with vertex-cluster bases from the normal derivative in y of Green's
+    formula: the GCA matrix approaches the dense Galerkin K as the tolerance
+    and the face order grow (a wrong sign or term in the second derivative
+    would stop the convergence)."""
+    v, t = synth.octa_sphere(8)
+    K = oracle.dlp_dense(v, t, 4)
+    x = synth.random_vector(len(v), 2)
+    errs = []
+    for m, eps in ((2, 1e-2), (3, 1e-4)):
+        A, info = gca.gca_dense_dlp(v, t, 16, m, eps, K)
+        assert info["far"] > 0
+        errs.append(np.linalg.norm(A @ x - K @ x) / np.linalg.norm(K @ x))
+    assert errs[0] > 50 * errs[1], errs
+    assert errs[1] < 1e-5, errs
