@@ -150,15 +150,16 @@ typedef struct {
                                pairs across leaves; the single-vector products G x and G^T x then
                                read about half the nearfield bytes (0.53x the nearfield storage
                                extra).  Ignored otherwise. */
-    double gca_tol;         /* > 0: far field of G by the Green cross approximation of Section 4
+    double gca_tol;         /* > 0: far field by the Green cross approximation of Section 4
                                instead of interpolation: order_m Gauss points per direction on each
                                face of the auxiliary box omega_t (B_t widened by its largest side),
                                cross approximation of [A C] with full pivoting stopped at gca_tol
                                relative to the first pivot, nested bases V_t by algebraic
-                               interpolation and couplings G|_{t_hat x s_hat} from the nearfield
-                               quadrature; bases built on the host.  Single-layer operator on one
-                               tree only (H2B_ENOTSUP otherwise); excludes recompress_tol (H2B_EINVAL);
-                               0 (default): interpolation */
+                               interpolation and couplings A|_{t_hat x s_hat} from the nearfield
+                               quadrature; bases built on the host.  For K the vertex clusters use
+                               the normal derivative in y of Green's formula (Section 5).  G must
+                               be on one tree (H2B_ENOTSUP otherwise); excludes recompress_tol
+                               (H2B_EINVAL); 0 (default): interpolation */
 } h2b_params;
 
 /* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64,

@@ -1,6 +1,7 @@
-// Green cross approximation (GCA, Section 4) of the single-layer matrix G:
-// nested cluster bases by "algebraic interpolation" and couplings made of
-// matrix entries, G|_{t x s} ~ V_t G|_{t_hat x s_hat} V_s^T.
+// Green cross approximation (GCA, Section 4) of the single-layer matrix G and
+// the double-layer matrix K: nested cluster bases by "algebraic
+// interpolation" and couplings made of matrix entries,
+// A|_{t x s} ~ V_t A|_{t_hat x s_hat} W_s^T.
 //
 // For every cluster t, bottom-up:
 //   1. omega_t = B_t widened by delta_t (the largest side of B_t) on every
@@ -14,9 +15,14 @@
 //      column pivots sigma;
 //   4. V = L|_{rows x sigma} (L|_{tau x sigma})^{-1}: the leaf basis V_t, or
 //      for a parent the stacked transfer matrices [E_1; E_2]; t_hat = rows[tau].
+// The vertex clusters of K's columns take the normal derivative in y of
+// Green's formula on omega_s instead (Section 5: K uses the derivatives of the
+// approximated kernel): L = [B D], b_{j nu} = w^{1/2} int phi_j(y)
+// dg/dn_y(y, z_nu) dy, d_{j nu} = w^{1/2} int phi_j(y) d2g/(dn_y dn_z)(y, z_nu) dy.
 // The host builds the bases (clusters of one level in parallel); the GPU
-// evaluates the coupling entries G|_{t_hat x s_hat} with the nearfield
-// quadrature kernel over panels whose rows and columns are pivot triangles.
+// evaluates the coupling entries A|_{t_hat x s_hat} with the nearfield
+// quadrature kernel over panels whose rows and columns are pivot triangles
+// (and pivot vertices for K's columns).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -94,6 +100,55 @@ void green_matrix(const Mesh &M, const std::vector<int32_t> &rows, const FaceRul
                     row[k + nu] += wt * dn;
                 }
             }
+        for (int nu = 0; nu < k; ++nu) {
+            row[nu] *= F.sw[nu];
+            row[k + nu] *= F.sw[nu];
+        }
+    }
+}
+
+// L = [B D] for the vertices `rows` (hat functions on the triangles around
+// each vertex, normal derivatives in y).
+void green_matrix_p1(const Mesh &M, const std::vector<int32_t> &rows, const FaceRule &F,
+                     const std::vector<double> &tq, const std::vector<double> &wq, std::vector<double> &L)
+{
+    const int k = F.k, q = (int)tq.size();
+    L.assign(rows.size() * 2 * (size_t)k, 0.0);
+    for (size_t r = 0; r < rows.size(); ++r) {
+        const int j = rows[r];
+        double *row = &L[r * 2 * (size_t)k];
+        for (int64_t e = M.vt_ptr[j]; e < M.vt_ptr[j + 1]; ++e) {
+            const int i = M.vt_idx[e];
+            const int a = M.t0[i], b = M.t1[i], c = M.t2[i];
+            const int corner = j == a ? 0 : j == b ? 1 : 2;
+            const double P0[3] = {M.vx[a], M.vy[a], M.vz[a]}, P1[3] = {M.vx[b], M.vy[b], M.vz[b]},
+                         P2[3] = {M.vx[c], M.vy[c], M.vz[c]};
+            double e1[3], e2[3];
+            for (int d = 0; d < 3; ++d) e1[d] = P1[d] - P0[d], e2[d] = P2[d] - P1[d];
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                         cz = e1[0] * e2[1] - e1[1] * e2[0];
+            const double jac = std::sqrt(cx * cx + cy * cy + cz * cz);
+            const double ny[3] = {cx / jac, cy / jac, cz / jac};
+            for (int qa = 0; qa < q; ++qa)
+                for (int qb = 0; qb < q; ++qb) {
+                    const double u1 = tq[qa], u2 = tq[qa] * tq[qb];
+                    const double lam = corner == 0 ? 1.0 - u1 : corner == 1 ? u1 - u2 : u2;
+                    const double wt = wq[qa] * wq[qb] * tq[qa] * jac * lam;
+                    double y[3];
+                    for (int d = 0; d < 3; ++d) y[d] = P0[d] + u1 * e1[d] + u2 * e2[d];
+                    for (int nu = 0; nu < k; ++nu) {
+                        const double dx = y[0] - F.z[3 * nu], dy = y[1] - F.z[3 * nu + 1], dz = y[2] - F.z[3 * nu + 2];
+                        const double r2 = dx * dx + dy * dy + dz * dz, rr = std::sqrt(r2);
+                        const double g3 = 1.0 / (FOUR_PI * rr * r2);  // 1 / (4 pi r^3)
+                        const double dny = dx * ny[0] + dy * ny[1] + dz * ny[2];
+                        const double* n = &F.n[3 * nu];
+                        const double dnz = dx * n[0] + dy * n[1] + dz * n[2];
+                        const double nn = ny[0] * n[0] + ny[1] * n[1] + ny[2] * n[2];
+                        row[nu] += wt * (-dny * g3);
+                        row[k + nu] += wt * (nn * g3 - 3.0 * dny * dnz * g3 / r2);
+                    }
+                }
+        }
         for (int nu = 0; nu < k; ++nu) {
             row[nu] *= F.sw[nu];
             row[k + nu] *= F.sw[nu];
@@ -204,7 +259,10 @@ GcaBases gca_bases(const Tree &T, int m, double eps)
             const double hi[3] = {bx[3] + delta, bx[4] + delta, bx[5] + delta};
             const FaceRule F = face_rule(lo, hi, m, t, w);
             std::vector<double> L;
-            green_matrix(M, rows, F, tq, wq, L);
+            if (T.space == H2B_P1)
+                green_matrix_p1(M, rows, F, tq, wq, L);
+            else
+                green_matrix(M, rows, F, tq, wq, L);
             const int nr = (int)rows.size(), ncol = 2 * F.k;
             std::vector<double> R = L;
             std::vector<int> tau, sigma;
@@ -224,11 +282,11 @@ GcaBases gca_bases(const Tree &T, int m, double eps)
     return G;
 }
 
-void set_gca_values(Op &op, const GcaBases &G, hipStream_t st)
+namespace {
+
+void set_gca_basis(Basis &B, const GcaBases &G, h2b_dtype dt, hipStream_t st)
 {
-    Basis &B = *op.rowb;
     const Tree &T = *B.tree;
-    const h2b_dtype dt = op.params.farfield_dtype;
     // leaf panels hold V_t^T (k_t x |t|), transfer panels [E_1^T | E_2^T]
     std::vector<double> leaf(std::max<int64_t>(B.leaf.total, 1)), tr(std::max<int64_t>(B.trans.total, 1));
     for (int g = 0; g < B.leaf.ngroups(); ++g) {
@@ -258,15 +316,31 @@ void set_gca_values(Op &op, const GcaBases &G, hipStream_t st)
     up(leaf, B.leaf_vals);
     up(tr, B.trans_vals);
     transpose_basis_values(B, dt, st);
+}
 
-    // couplings: entries G_{i j} for the pivot triangles i of t_hat, j of s_hat
-    std::vector<int32_t> hidx(std::max<int64_t>(B.hat_total, 1), 0);
-    for (int64_t c = 0; c < T.nclusters(); ++c)
-        for (int i = 0; i < G.rank[c]; ++i) hidx[B.hat_off[c] + i] = G.hat[c][i];
-    DevMem dh;
-    dh.alloc(sizeof(int32_t) * hidx.size());
-    hip_check(hipMemcpyAsync(dh.p, hidx.data(), sizeof(int32_t) * hidx.size(), hipMemcpyHostToDevice, st),
-              "upload");
+// Original index of the pivot at every coefficient position of a basis.
+void upload_pivots(const Basis &B, const GcaBases &G, DevMem &mem, hipStream_t st)
+{
+    std::vector<int32_t> h(std::max<int64_t>(B.hat_total, 1), 0);
+    for (int64_t c = 0; c < B.tree->nclusters(); ++c)
+        for (int i = 0; i < G.rank[c]; ++i) h[B.hat_off[c] + i] = G.hat[c][i];
+    mem.alloc(sizeof(int32_t) * h.size());
+    hip_check(hipMemcpyAsync(mem.p, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipStreamSynchronize(st), "upload");
+}
+
+}  // namespace
+
+void set_gca_values(Op &op, const GcaBases &Gr, const GcaBases &Gc, hipStream_t st)
+{
+    const h2b_dtype dt = op.params.farfield_dtype;
+    set_gca_basis(*op.rowb, Gr, dt, st);
+    if (op.colb != op.rowb) set_gca_basis(*op.colb, Gc, dt, st);
+    DevMem rh, ch;
+    upload_pivots(*op.rowb, Gr, rh, st);
+    if (op.colb != op.rowb) upload_pivots(*op.colb, Gc, ch, st);
+    const int32_t *rperm = rh.as<int32_t>(), *cperm = op.colb != op.rowb ? ch.as<int32_t>() : rperm;
+    // couplings: entries A_{i j} for the pivots i of t_hat and j of s_hat
     const int64_t n = std::max<int64_t>(op.cpl.total, 1);
     DevMem s64;
     double *dst = nullptr;
@@ -277,8 +351,7 @@ void set_gca_values(Op &op, const GcaBases &G, hipStream_t st)
         s64.alloc(sizeof(double) * n);
         dst = s64.as<double>();
     }
-    launch_near_assemble(H2B_SLP, op.cpl, dh.as<int32_t>(), dh.as<int32_t>(), op.geo, make_quad(op.params.q_near), dst,
-                         st);
+    launch_near_assemble(op.kernel, op.cpl, rperm, cperm, op.geo, make_quad(op.params.q_near), dst, st);
     if (dt != H2B_F64) {
         op.cpl_vals.alloc(coupling_size(dt) * n);
         const int nb = (int)std::min<int64_t>((n + 255) / 256, 65536);

@@ -223,8 +223,8 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (!(p.gca_tol >= 0.0) || !std::isfinite(p.gca_tol)) fail(H2B_EINVAL, "gca_tol must be finite and >= 0");
     const bool gca = p.gca_tol > 0.0;
     if (gca && p.recompress_tol > 0.0) fail(H2B_EINVAL, "choose either recompression or the Green cross approximation");
-    if (gca && (kernel != H2B_SLP || blocks->rows != blocks->cols))
-        fail(H2B_ENOTSUP, "the Green cross approximation is built for the single-layer matrix on one tree");
+    if (gca && kernel == H2B_SLP && blocks->rows != blocks->cols)
+        fail(H2B_ENOTSUP, "the Green cross approximation of G needs one cluster tree");
 
     auto op = std::make_unique<Op>();
     op->blocks = blocks;
@@ -273,10 +273,14 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (op->colb != op->rowb) bases.push_back(op->colb.get());
     // Green cross approximation: pivots and nested bases first (host), their
     // ranks shape the basis and coupling panels
-    GcaBases gb;
-    if (gca) gb = gca_bases(R, m, p.gca_tol);
+    GcaBases gb, gbc;
+    if (gca) {
+        gb = gca_bases(R, m, p.gca_tol);
+        if (op->colb != op->rowb) gbc = gca_bases(C, m, p.gca_tol);
+    }
     for (Basis *B : bases) {
-        build_basis_structure(*B, gca ? gb.rank : std::vector<int>(B->tree->nclusters(), k), st);
+        const std::vector<int> &gr = B == op->rowb.get() ? gb.rank : gbc.rank;
+        build_basis_structure(*B, gca ? gr : std::vector<int>(B->tree->nclusters(), k), st);
         B->leaf.upload(st);
         B->leaf_T.upload(st);
         B->trans.upload(st);
@@ -327,7 +331,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     const bool rc = p.recompress_tol > 0.0;
     const h2b_dtype adt = rc ? H2B_F64 : p.farfield_dtype;
     if (gca) {
-        set_gca_values(*op, gb, st);
+        set_gca_values(*op, gb, op->colb != op->rowb ? gbc : gb, st);
     } else {
     op->cpl_vals.alloc(coupling_size(adt) * std::max<int64_t>(op->cpl.total, 1));
     for (Basis *B : bases) {

@@ -112,8 +112,9 @@ inline size_t coupling_size(h2b_dtype dt)
 
 QuadDev make_quad(int q);
 
-// Green cross approximation of G on one tree: per cluster the rank k_t, the
-// pivot triangles t_hat (original indices, pivot order) and V, the leaf basis
+// Green cross approximation on one tree (triangles, or the vertices of K's
+// columns): per cluster the rank k_t, the pivots t_hat (original indices,
+// pivot order) and V, the leaf basis
 // (|t| x k_t, position order) or the stacked transfers [E_1; E_2]
 // ((k_1 + k_2) x k_t), both row-major.
 struct GcaBases {
@@ -122,9 +123,10 @@ struct GcaBases {
     std::vector<std::vector<double>> V;
 };
 GcaBases gca_bases(const Tree &T, int m, double eps);
-// Basis values (in the far-field dtype) and coupling entries G|_{t_hat x s_hat}
-// of an operator whose panels were built with the GCA ranks.
-void set_gca_values(Op &op, const GcaBases &G, hipStream_t st);
+// Basis values (in the far-field dtype) and coupling entries A|_{t_hat x s_hat}
+// of an operator whose panels were built with the GCA ranks (Gr: row tree,
+// Gc: column tree, the same object for G).
+void set_gca_values(Op &op, const GcaBases &Gr, const GcaBases &Gc, hipStream_t st);
 
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
