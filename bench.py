@@ -324,6 +324,53 @@ def ntd_solve(torch, h2b, ops, verts, tris):
     return d
 
 
+def gca_solve(torch, h2b, mesh, verts, tris, args):
+    """Dirichlet-to-Neumann solve with the Green cross approximation (order
+    args.gca_order per face direction, tolerance args.gca_tol) for both G and
+    K, no transposed copies (the solve uses G x and K x only): setup, storage,
+    product time and the L2 error of the Neumann data of u1 = x1^2 - x3^2."""
+    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, GCA order %d tol %g, CG tol 1e-8"
+                      % (args.gca_order, args.gca_tol)}
+    kw = dict(leaf=args.leaf, order_m=args.gca_order, q_near=args.q_near, gca_tol=args.gca_tol,
+              transposed_copy=False, mesh=mesh)
+    gops = {}
+    for name, kern in (("G", "slp"), ("K", "dlp")):
+        t0 = time.perf_counter()
+        gops[name] = h2b.Operator(kernel=kern, **kw)
+        torch.cuda.synchronize()
+        inf = gops[name].info()
+        res[name] = {"setup_s": round(time.perf_counter() - t0, 1), "bytes_far": inf["bytes_far"],
+                     "bytes_near": inf["bytes_near"], "mean_rank": (inf["mean_rank_row"], inf["mean_rank_col"]),
+                     "max_rank": (inf["max_rank_row"], inf["max_rank_col"])}
+        log("GCA %s: setup %.1f s, far %.2f GB, mean ranks %.1f / %.1f" % (
+            name, res[name]["setup_s"], inf["bytes_far"] / 1e9, inf["mean_rank_row"], inf["mean_rank_col"]))
+    G = gops["G"]
+    x = torch.tensor(synth_vector(len(tris)), device="cuda")
+    y = torch.zeros_like(x)
+    G.matvec(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        G.matvec(x, y)
+    torch.cuda.synchronize()
+    res["G"]["ms_Ax"] = round((time.perf_counter() - t0) * 1e3 / 5, 4)
+    u = torch.tensor(verts[:, 0] ** 2 - verts[:, 2] ** 2, dtype=torch.float64, device="cuda")
+    b = h2b.dtn_rhs(gops["K"], u)
+    t = torch.zeros_like(b)
+    r = G.cg(b, t, tol=1e-8, max_iter=3000)
+    res["cg"] = {"iterations": r["iterations"], "status": r["status"], "solve_ms": round(r["solve_ms"], 1),
+                 "rel_residual": r["rel_residual"]}
+    res["l2_error_neumann"] = neumann_l2_error_u1(verts, tris, t.cpu().numpy())
+    log("GCA DtN solve: %d iterations, %.1f ms, L2 error %.4e" % (r["iterations"], r["solve_ms"],
+                                                                 res["l2_error_neumann"]))
+    return res
+
+
+def synth_vector(n):
+    import synth
+    return synth.random_vector(n, 501)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +385,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
+    ap.add_argument("--gca-solve", action="store_true",
+                    help="also solve the Dirichlet-to-Neumann system with GCA operators (minutes of setup)")
+    ap.add_argument("--gca-order", type=int, default=4)
+    ap.add_argument("--gca-tol", type=float, default=1e-6)
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the Dirichlet-to-Neumann and Neumann-to-Dirichlet CG solves")
     ap.add_argument("--copy-calib", action="store_true",
@@ -548,6 +599,13 @@ def main():
 
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))
+
+    if args.gca_solve:
+        # the benchmark operators make room for the GCA pair
+        dop = None
+        ops.clear()
+        torch.cuda.empty_cache()
+        out["gca_solve"] = gca_solve(torch, h2b, mesh, verts, tris, args)
 
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
