@@ -100,6 +100,55 @@ def cg(apply_a, b, tol, max_iter, x0=None):
     return x, k, np.array(history)
 
 
+def pcg(apply_a, apply_m, b, tol, max_iter):
+    """Preconditioned conjugate gradients from x = 0 with the symmetric
+    positive definite preconditioner z = apply_m(r): rho = r^T z, the same
+    stopping rule on ||r|| as cg().  Returns (x, iterations, history)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = math.sqrt(float(b @ b))
+    scale = bnorm if bnorm > 0 else 1.0
+    z = apply_m(r)
+    rho = float(r @ z)
+    p = z.copy()
+    history = [math.sqrt(float(r @ r)) / scale]
+    k = 0
+    while history[-1] * scale > tol * bnorm and k < max_iter:
+        q = apply_a(p)
+        pq = float(p @ q)
+        if not pq > 0:
+            break
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        z = apply_m(r)
+        rho_new = float(r @ z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+        k += 1
+        history.append(math.sqrt(float(r @ r)) / scale)
+    return x, k, np.array(history)
+
+
+def block_jacobi(A, blocks):
+    """Block-diagonal preconditioner: the inverses of the symmetric parts of
+    the diagonal blocks A[idx, idx] for the index lists `blocks`, returned as
+    a function r -> z."""
+    inv = []
+    for idx in blocks:
+        B = A[np.ix_(idx, idx)]
+        inv.append((idx, np.linalg.inv(0.5 * (B + B.T))))
+
+    def apply(r):
+        z = np.zeros_like(r)
+        for idx, Bi in inv:
+            z[idx] = Bi @ r[idx]
+        return z
+
+    return apply
+
+
 def dtn_matrices(verts, tris, q):
     """Dense G, K and M of one mesh (nearfield quadrature order q everywhere)."""
     return slp_dense(verts, tris, q), dlp_dense(verts, tris, q), mass_matrix(verts, tris)

@@ -116,6 +116,27 @@ def test_cg_stopping_rule_and_degenerate_cases():
     assert k == 0 and not x.any()
 
 
+def test_pcg_limits():
+    """Preconditioned CG: with the identity it is CG step for step; with the
+    exact inverse it converges in one step; with block-Jacobi on a
+    block-diagonal SPD matrix it converges in one step."""
+    n = 24
+    A = _spd(n, np.geomspace(1.0, 100.0, n), 12)
+    b = np.random.default_rng(13).standard_normal(n)
+    x0, k0, h0 = krylov.cg(lambda p: A @ p, b, 1e-10, 200)
+    x1, k1, h1 = krylov.pcg(lambda p: A @ p, lambda r: r.copy(), b, 1e-10, 200)
+    assert k0 == k1 and np.allclose(h0, h1, rtol=1e-9, atol=0)
+    Ai = np.linalg.inv(A)
+    _, k2, _ = krylov.pcg(lambda p: A @ p, lambda r: Ai @ r, b, 1e-10, 200)
+    assert k2 == 1
+    blocks = [np.arange(0, 10), np.arange(10, 16), np.arange(16, 24)]
+    D = np.zeros((n, n))
+    for idx in blocks:
+        D[np.ix_(idx, idx)] = _spd(len(idx), np.geomspace(1.0, 30.0, len(idx)), 20 + len(idx))
+    _, k3, _ = krylov.pcg(lambda p: D @ p, krylov.block_jacobi(D, blocks), b, 1e-10, 200)
+    assert k3 == 1
+
+
 # ----------------------------------------------------- Dirichlet-to-Neumann
 
 def test_l2_error_of_exact_and_shifted_data():
