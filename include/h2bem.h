@@ -374,10 +374,22 @@ h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, dou
  * of max_iter + 1 doubles receiving ||r_k|| / ||b|| for k = 0..iterations.
  * Work vectors (3 n doubles plus small state) are allocated per call.  The
  * call synchronises hip_stream and returns when the solve has ended.
+ * precond = H2B_PRECOND_BLOCK_JACOBI runs preconditioned CG (rho = r^T z,
+ * z = P r) with P the block-diagonal matrix of the inverses of the symmetric
+ * parts of the diagonal nearfield blocks N_tt of the leaves (G on one tree,
+ * leaves of at most 64; product form only).  The inverses are computed on
+ * the device by the first such solve (sum of |t|^2 doubles, kept by the
+ * operator); applying P reads them once per iteration.  The stopping test
+ * and the residuals stay on ||r||.  This is not the paper's H-Cholesky
+ * preconditioner.
+ *
  * Errors: H2B_EINVAL for a non-square operator (not the single-layer
- * operator for the hypersingular form), an unknown form, NULL or overlapping
- * b and x, tol < 0 or not finite, max_iter < 0, check_every < 1. */
+ * operator for the hypersingular form), an unknown form or preconditioner,
+ * NULL or overlapping b and x, tol < 0 or not finite, max_iter < 0,
+ * check_every < 1; H2B_ENOTSUP for the block-Jacobi preconditioner on other
+ * operators, larger leaves or the hypersingular form. */
 typedef enum { H2B_FORM_PRODUCT = 0, H2B_FORM_HYPERSINGULAR = 1 } h2b_cg_form;
+typedef enum { H2B_PRECOND_NONE = 0, H2B_PRECOND_BLOCK_JACOBI = 1 } h2b_cg_precond;
 
 typedef struct {
     double tol;        /* relative residual to reach (default 1e-8) */
@@ -386,6 +398,7 @@ typedef struct {
     int use_graph;     /* 1: replay a HIP graph of check_every iterations (default 1) */
     int zero_guess;    /* 1: start from x = 0 without the initial product (default 1) */
     int form;          /* h2b_cg_form: the operator's product (default) or W built from G */
+    int precond;       /* h2b_cg_precond: none (default) or block Jacobi, see below */
 } h2b_cg_params;
 
 typedef enum { H2B_CG_CONVERGED = 1, H2B_CG_BREAKDOWN = 2, H2B_CG_MAXITER = 3 } h2b_cg_status;

@@ -56,7 +56,8 @@ class h2b_op_stats(ctypes.Structure):
 
 class h2b_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int), ("form", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int), ("form", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class h2b_cg_result(ctypes.Structure):
@@ -67,6 +68,8 @@ class h2b_cg_result(ctypes.Structure):
 H2B_CG_CONVERGED, H2B_CG_BREAKDOWN, H2B_CG_MAXITER = 1, 2, 3
 H2B_FORM_PRODUCT, H2B_FORM_HYPERSINGULAR = 0, 1
 _FORMS = {"product": H2B_FORM_PRODUCT, "hypersingular": H2B_FORM_HYPERSINGULAR}
+H2B_PRECOND_NONE, H2B_PRECOND_BLOCK_JACOBI = 0, 1
+_PRECONDS = {None: H2B_PRECOND_NONE, "none": H2B_PRECOND_NONE, "block_jacobi": H2B_PRECOND_BLOCK_JACOBI}
 CG_STATUS = {H2B_CG_CONVERGED: "converged", H2B_CG_BREAKDOWN: "breakdown", H2B_CG_MAXITER: "max_iter"}
 
 
@@ -315,10 +318,12 @@ class Operator:
         return y
 
     def cg(self, b, x, tol=1e-8, max_iter=1000, check_every=8, use_graph=True, zero_guess=True,
-           history=False, form="product", stream=None):
+           history=False, form="product", precond=None, stream=None):
         """Conjugate gradients for A x = b (A square, symmetric positive
         definite: the single-layer matrix G), or with form="hypersingular"
-        for W x = b, W built from this single-layer operator.  x holds the
+        for W x = b, W built from this single-layer operator; precond=
+        "block_jacobi" preconditions with the inverse diagonal nearfield
+        blocks of the leaves.  x holds the
         initial guess (unless zero_guess) and receives the solution.  Returns
         a dict with iterations, status, rel_residual, solve_ms and, with
         history, the relative residual norms of iterations 0..iterations."""
@@ -337,6 +342,7 @@ class Operator:
         p.tol, p.max_iter, p.check_every = float(tol), int(max_iter), int(check_every)
         p.use_graph, p.zero_guess = int(bool(use_graph)), int(bool(zero_guess))
         p.form = _FORMS[form]
+        p.precond = _PRECONDS[precond]
         r = h2b_cg_result()
         hist = np.zeros(max(int(max_iter), 0) + 1) if history else None
         _check(h2b_cg_solve(self.handle, _vp(b.data_ptr()), _vp(x.data_ptr()), ctypes.byref(p), ctypes.byref(r),

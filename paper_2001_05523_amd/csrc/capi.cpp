@@ -315,6 +315,7 @@ void h2b_cg_params_default(h2b_cg_params *p)
     p->use_graph = 1;
     p->zero_guess = 1;
     p->form = H2B_FORM_PRODUCT;
+    p->precond = H2B_PRECOND_NONE;
 }
 
 h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, double *y, void *hip_stream)

@@ -30,7 +30,8 @@ constexpr int KMAXB = 1024;  // most partial sums of one reduction
 
 // State of one solve in device memory.
 struct CgState {
-    double rho;      // r^T r of the current residual
+    double rho;      // r^T z of the current residual (z = r without a preconditioner)
+    double rr;       // r^T r (the stopping test and the reported residual)
     double bnorm2;   // b^T b
     double thresh2;  // (tol ||b||)^2
     double alpha, beta;
@@ -88,17 +89,21 @@ __global__ __launch_bounds__(KT) void k_copy(const double *__restrict__ src, dou
     for (int64_t i = blockIdx.x * (int64_t)KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) dst[i] = src[i];
 }
 
-// Initial state from the partial sums of b^T b and r0^T r0.
+// Initial state from the partial sums of b^T b, r0^T r0 and (preconditioned)
+// r0^T z0 (prz = NULL: z0 = r0).
 __global__ __launch_bounds__(KT) void k_cg_start(const double *__restrict__ pb, const double *__restrict__ pr,
-                                                 int nb, double tol, int max_iter, CgState *S, double *hist)
+                                                 const double *__restrict__ prz, int nb, double tol, int max_iter,
+                                                 CgState *S, double *hist)
 {
     __shared__ double lds[KT / 64];
     const double bb = parts_total(pb, nb, lds);
     const double rr = parts_total(pr, nb, lds);
+    const double rz = prz ? parts_total(prz, nb, lds) : rr;
     if (threadIdx.x == 0) {
         S->bnorm2 = bb;
         S->thresh2 = tol * tol * bb;
-        S->rho = rr;
+        S->rho = rz;
+        S->rr = rr;
         S->alpha = 0.0;
         S->beta = 0.0;
         S->iter = 0;
@@ -167,17 +172,21 @@ __global__ __launch_bounds__(KT) void k_cg_step(double *__restrict__ x, double *
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// rho' = r^T r, beta = rho' / rho, count the iteration and test the stop.
-__global__ __launch_bounds__(KT) void k_cg_beta(const double *__restrict__ part, int nb, CgState *S, double *hist)
+// rr' = r^T r, rho' = r^T z (prz = NULL: rho' = rr'), beta = rho' / rho,
+// count the iteration and test the stop on rr'.
+__global__ __launch_bounds__(KT) void k_cg_beta(const double *__restrict__ part, const double *__restrict__ prz,
+                                                int nb, CgState *S, double *hist)
 {
     __shared__ double lds[KT / 64];
     const double rr = parts_total(part, nb, lds);
+    const double rz = prz ? parts_total(prz, nb, lds) : rr;
     if (threadIdx.x == 0) {
         double b = 0.0;
         if (S->status == 0) {
             const int it = S->iter + 1;
-            b = rr / S->rho;
-            S->rho = rr;
+            b = rz / S->rho;
+            S->rho = rz;
+            S->rr = rr;
             S->iter = it;
             hist[it] = rel_norm(rr, S->bnorm2);
             if (rr <= S->thresh2)
@@ -189,7 +198,7 @@ __global__ __launch_bounds__(KT) void k_cg_beta(const double *__restrict__ part,
     }
 }
 
-// p = r + beta p.
+// p = z + beta p (z = r without a preconditioner).
 __global__ __launch_bounds__(KT) void k_cg_direction(double *__restrict__ p, const double *__restrict__ r, int64_t n,
                                                      const CgState *S)
 {
@@ -290,6 +299,62 @@ __global__ __launch_bounds__(KT) void k_curl_t(GeoDev g, int64_t nv, int64_t nt,
     }
 }
 
+// Block-Jacobi preconditioner: the inverse of the symmetric part of every
+// diagonal nearfield block N_tt (leaves of at most 64), by Gauss-Jordan
+// elimination in LDS (no pivoting: the blocks of G are symmetric positive
+// definite).  One workgroup per leaf.
+__global__ __launch_bounds__(KT) void k_bj_invert(const int64_t *__restrict__ src, const int32_t *__restrict__ stride,
+                                                  const int32_t *__restrict__ nn, const int64_t *__restrict__ dst,
+                                                  const double *__restrict__ near, double *__restrict__ inv)
+{
+    __shared__ double A[64][65];
+    __shared__ double fcol[64];
+    __shared__ double piv;
+    const int leaf = blockIdx.x, n = nn[leaf], ld = stride[leaf];
+    const int64_t s0 = src[leaf];
+    for (int e = threadIdx.x; e < n * n; e += KT) {
+        const int i = e / n, j = e % n;
+        A[i][j] = 0.5 * (near[s0 + (int64_t)i * ld + j] + near[s0 + (int64_t)j * ld + i]);
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) piv = 1.0 / A[k][k];
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += KT) A[k][j] = j == k ? piv : A[k][j] * piv;
+        for (int i = threadIdx.x; i < n; i += KT) fcol[i] = i == k ? 0.0 : A[i][k];
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += KT) {
+            const int i = e / n, j = e % n;
+            if (i == k) continue;
+            A[i][j] = j == k ? -fcol[i] * A[k][k] : A[i][j] - fcol[i] * A[k][j];
+        }
+        __syncthreads();
+    }
+    const int64_t d0 = dst[leaf];
+    for (int e = threadIdx.x; e < n * n; e += KT) inv[d0 + e] = A[e / n][e % n];
+}
+
+// z|_t = inv_t r|_t for every leaf t (positions begin..begin+n of the
+// cluster order, original indices through perm); a wave per row, lanes
+// over the columns.
+__global__ __launch_bounds__(KT) void k_bj_apply(const int32_t *__restrict__ begin, const int32_t *__restrict__ nn,
+                                                 const int64_t *__restrict__ dst, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ inv, const double *__restrict__ r,
+                                                 double *__restrict__ z)
+{
+    __shared__ double rl[64];
+    const int leaf = blockIdx.x, n = nn[leaf], b = begin[leaf];
+    const int64_t d0 = dst[leaf];
+    if (threadIdx.x < n) rl[threadIdx.x] = r[perm[b + threadIdx.x]];
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = w; i < n; i += KT / 64) {
+        double v = lane < n ? inv[d0 + (int64_t)i * n + lane] * rl[lane] : 0.0;
+        v = wave_total(v);
+        if (lane == 0) z[perm[b + i]] = v;
+    }
+}
+
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(KMAXB, (n + KT * 4 - 1) / (KT * 4))); }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb)
@@ -300,7 +365,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb)
 
 // Owner of the resources of one solve.
 struct CgRun {
-    DevMem r, p, q, part, part2, state, hist, w1, bp;
+    DevMem r, p, q, part, part2, state, hist, w1, bp, z, part3;
     CgState *host = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -328,6 +393,47 @@ void mass_matvec(Op &op, int trans, double alpha, const double *x, double *y, hi
     else
         hipLaunchKernelGGL(k_mass, dim3(grid_for(nout)), dim3(KT), 0, st, op.geo, nout, alpha, x, y);
     hip_check(hipGetLastError(), "mass launch");
+}
+
+// Inverse diagonal blocks of the nearfield, once per operator.
+static void prepare_block_jacobi(Op &A, hipStream_t st)
+{
+    if (A.bj_leaves > 0) return;
+    if (A.kernel != H2B_SLP || A.blocks->rows != A.blocks->cols)
+        fail(H2B_ENOTSUP, "the block-Jacobi preconditioner needs the single-layer operator on one tree");
+    if (A.near.max_nrows > 64) fail(H2B_ENOTSUP, "the block-Jacobi preconditioner needs leaves of at most 64");
+    const RowPanels &N = A.near;
+    std::vector<int64_t> src, dst;
+    std::vector<int32_t> stride, nn, begin;
+    int64_t tot = 0;
+    for (int g = 0; g < N.ngroups(); ++g) {
+        const int t = N.group_tag[g];
+        int seg = -1;
+        for (int q = N.seg_ptr[g]; q < N.seg_ptr[g + 1]; ++q)
+            if (N.seg_tag[q] == t) seg = q;
+        if (seg < 0) fail(H2B_EDEVICE, "a leaf without its diagonal nearfield block");
+        src.push_back(N.val_off[g] + N.seg_c0[seg]);
+        stride.push_back(N.ncols[g]);
+        nn.push_back(N.nrows[g]);
+        begin.push_back(N.out_begin[g]);
+        dst.push_back(tot);
+        tot += (int64_t)N.nrows[g] * N.nrows[g];
+    }
+    Packer pk;
+    const int64_t *d_src = nullptr;
+    const int32_t *d_stride = nullptr;
+    pk.add(src, const_cast<int64_t **>(&d_src));
+    pk.add(dst, const_cast<int64_t **>(&A.bj_dst));
+    pk.add(stride, const_cast<int32_t **>(&d_stride));
+    pk.add(nn, const_cast<int32_t **>(&A.bj_n));
+    pk.add(begin, const_cast<int32_t **>(&A.bj_begin));
+    pk.upload(A.bj_mem, st);
+    A.bj_inv.alloc(sizeof(double) * std::max<int64_t>(tot, 1));
+    hipLaunchKernelGGL(k_bj_invert, dim3(N.ngroups()), dim3(KT), 0, st, d_src, d_stride, A.bj_n, A.bj_dst,
+                       A.near_vals.as<double>(), A.bj_inv.as<double>());
+    hip_check(hipGetLastError(), "block-Jacobi setup");
+    hip_check(hipStreamSynchronize(st), "block-Jacobi setup");
+    A.bj_leaves = N.ngroups();
 }
 
 static void check_single_layer(const Op &G)
@@ -372,6 +478,10 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     const auto t0 = std::chrono::steady_clock::now();
     const bool hyp = prm.form == H2B_FORM_HYPERSINGULAR;
     if (prm.form != H2B_FORM_PRODUCT && !hyp) fail(H2B_EINVAL, "unknown operator form");
+    if (prm.precond != H2B_PRECOND_NONE && prm.precond != H2B_PRECOND_BLOCK_JACOBI)
+        fail(H2B_EINVAL, "unknown preconditioner");
+    const bool pc = prm.precond == H2B_PRECOND_BLOCK_JACOBI;
+    if (pc && hyp) fail(H2B_ENOTSUP, "the block-Jacobi preconditioner is built for the product form");
     if (hyp) check_single_layer(A);
     if (!hyp && A.nrows != A.ncols) fail(H2B_EINVAL, "conjugate gradients need a square operator");
     const int64_t n = hyp ? A.blocks->rows->mesh->nv : A.nrows;
@@ -391,6 +501,7 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         prepare_hypersingular(A);
     else
         prepare_product(A, 1);
+    if (pc) prepare_block_jacobi(A, st);
 
     CgRun w;
     const int nb = grid_for(n);
@@ -403,6 +514,17 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     w.hist.alloc(sizeof(double) * ((size_t)prm.max_iter + 1));
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&w.host), sizeof(CgState), hipHostMallocDefault),
               "pinned state");
+    if (pc) {
+        w.z.alloc(sizeof(double) * n);
+        w.part3.alloc(sizeof(double) * KMAXB);
+    }
+    double *z = pc ? w.z.as<double>() : nullptr, *part3 = pc ? w.part3.as<double>() : nullptr;
+    // z = P r (block Jacobi) for the leaves of the operator's row tree
+    auto precondition = [&](hipStream_t s) {
+        hipLaunchKernelGGL(k_bj_apply, dim3(A.bj_leaves), dim3(KT), 0, s, A.bj_begin, A.bj_n, A.bj_dst,
+                           A.rowb->perm_dev, A.bj_inv.as<double>(), w.r.as<double>(), z);
+        hipLaunchKernelGGL(k_dot_part, dim3(grid_for(n)), dim3(KT), 0, s, w.r.as<double>(), z, n, part3);
+    };
     double *r = w.r.as<double>(), *p = w.p.as<double>(), *q = w.q.as<double>();
     double *part = w.part.as<double>(), *part2 = w.part2.as<double>(), *hist = w.hist.as<double>();
     CgState *S = w.state.as<CgState>();
@@ -428,8 +550,10 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     if (!prm.zero_guess) apply(x, r, -1.0, st);
     hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, b, b, n, part);
     hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, r, r, n, part2);
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(KT), 0, st, part, part2, nb, prm.tol, prm.max_iter, S, hist);
-    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(KT), 0, st, r, p, n);
+    if (pc) precondition(st);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(KT), 0, st, part, part2, part3, nb, prm.tol, prm.max_iter, S,
+                       hist);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(KT), 0, st, pc ? z : r, p, n);
     launch_fill_zero<double>(q, n, st);
     hip_check(hipGetLastError(), "cg start");
 
@@ -438,8 +562,9 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, s, p, q, n, part);
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(KT), 0, s, part, nb, S);
         hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(KT), 0, s, x, r, p, q, n, S, part2);
-        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(KT), 0, s, part2, nb, S, hist);
-        hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(KT), 0, s, p, r, n, S);
+        if (pc) precondition(s);
+        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(KT), 0, s, part2, part3, nb, S, hist);
+        hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(KT), 0, s, p, pc ? z : r, n, S);
         hip_check(hipGetLastError(), "cg iteration");
     };
     auto read_state = [&] {
@@ -499,7 +624,7 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
                   "history read");
     res.iterations = cur.iter;
     res.status = cur.status;
-    res.rel_residual = sqrt(cur.bnorm2 > 0.0 ? cur.rho / cur.bnorm2 : cur.rho);
+    res.rel_residual = sqrt(cur.bnorm2 > 0.0 ? cur.rr / cur.bnorm2 : cur.rr);
     res.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

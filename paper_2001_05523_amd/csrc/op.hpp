@@ -95,6 +95,12 @@ struct Op {
     bool overlap = true;                    // false: the nearfield stays on the caller's stream
     DevMem gxp, gyp, gax, gay;              // shape-gradient work vectors
     DevMem hs_c, hs_g;                      // hypersingular product: curls and G times curls (3 nt each)
+    // block-Jacobi preconditioner (built by the first preconditioned solve):
+    // per leaf its first position, size and the offset of its inverse block
+    DevMem bj_inv, bj_mem;
+    const int32_t *bj_begin = nullptr, *bj_n = nullptr;
+    const int64_t *bj_dst = nullptr;
+    int bj_leaves = 0;
     int mrhs_rb = 0;                        // block width the block vectors are sized for
     int tune_rb = 0, tune_kc = 32;          // autotuned coupling tile (0: not tuned)
     bool timing = false;
