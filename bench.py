@@ -272,6 +272,14 @@ def dtn_solve(torch, h2b, ops, verts, tris, suffixes, ms_gx):
              "l2_error_neumann": neumann_l2_error_u1(verts, tris, sols[suffix])}
         if ms_gx.get(suffix):
             d["iteration_over_product"] = round(r["solve_ms"] / it / ms_gx[suffix], 3)
+        if not suffix:
+            tp = torch.zeros_like(b)
+            rp = G.cg(b, tp, tol=1e-8, max_iter=3000, precond="block_jacobi")
+            d["block_jacobi"] = {"iterations": rp["iterations"], "status": rp["status"],
+                                 "solve_ms": round(rp["solve_ms"], 2), "rel_residual": rp["rel_residual"],
+                                 "rel_diff_vs_cg": float(torch.linalg.norm(tp - t) / torch.linalg.norm(t))}
+            log("DtN solve with block-Jacobi: %d iterations, %.1f ms (setup of the inverses included)"
+                % (rp["iterations"], rp["solve_ms"]))
         res["f64" if not suffix else "mixed"] = d
         log("DtN solve (%s): %d iterations, %.1f ms (%.3f ms per iteration; eager %.1f ms), "
             "residual %.2e (true %.2e), L2 error %.3e" % ("f64" if not suffix else "mixed", r["iterations"],
@@ -329,7 +337,7 @@ def gca_solve(torch, h2b, mesh, verts, tris, args):
     args.gca_order per face direction, tolerance args.gca_tol) for both G and
     K, no transposed copies (the solve uses G x and K x only): setup, storage,
     product time and the L2 error of the Neumann data of u1 = x1^2 - x3^2."""
-    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, GCA order %d tol %g, CG tol 1e-8"
+    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, GCA order %d tol %g, block-Jacobi PCG tol 1e-8"
                       % (args.gca_order, args.gca_tol)}
     kw = dict(leaf=args.leaf, order_m=args.gca_order, q_near=args.q_near, gca_tol=args.gca_tol,
               transposed_copy=False, mesh=mesh)
@@ -357,7 +365,7 @@ def gca_solve(torch, h2b, mesh, verts, tris, args):
     u = torch.tensor(verts[:, 0] ** 2 - verts[:, 2] ** 2, dtype=torch.float64, device="cuda")
     b = h2b.dtn_rhs(gops["K"], u)
     t = torch.zeros_like(b)
-    r = G.cg(b, t, tol=1e-8, max_iter=3000)
+    r = G.cg(b, t, tol=1e-8, max_iter=3000, precond="block_jacobi")
     res["cg"] = {"iterations": r["iterations"], "status": r["status"], "solve_ms": round(r["solve_ms"], 1),
                  "rel_residual": r["rel_residual"]}
     res["l2_error_neumann"] = neumann_l2_error_u1(verts, tris, t.cpu().numpy())
