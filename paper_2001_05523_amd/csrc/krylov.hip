@@ -279,21 +279,36 @@ __global__ __launch_bounds__(KT) void k_curl(GeoDev g, int64_t nt, const double 
     }
 }
 
-// y_j += alpha sum over the triangles t around vertex j of
-// sum_d (curl phi_j on t)_d gc[t + d nt]  (the transpose of k_curl).
-__global__ __launch_bounds__(KT) void k_curl_t(GeoDev g, int64_t nv, int64_t nt, const double *__restrict__ gc,
-                                               double alpha, double *__restrict__ y)
+// The transpose of k_curl in two passes.  First, per triangle t, the three
+// corner contributions ct[3 t + c] = sum_d (curl phi_corner c on t)_d gc[t + d nt]
+// (one area per triangle, coalesced); then, per vertex j,
+// y_j += alpha sum over the triangles t around j of ct[3 t + (corner of j in t)].
+__global__ __launch_bounds__(KT) void k_curl_corners(GeoDev g, int64_t nt, const double *__restrict__ gc,
+                                                     double *__restrict__ ct)
+{
+    for (int64_t t = blockIdx.x * (int64_t)KT + threadIdx.x; t < nt; t += (int64_t)gridDim.x * KT) {
+        const int32_t a = g.t0[t], b = g.t1[t], d = g.t2[t];
+        const double inv2a = 1.0 / (2.0 * tri_area(g, t));
+        const double gx = gc[t], gy = gc[t + nt], gz = gc[t + 2 * nt];
+        double cx, cy, cz;
+        corner_curl(g, b, d, inv2a, cx, cy, cz);
+        ct[3 * t] = cx * gx + cy * gy + cz * gz;
+        corner_curl(g, d, a, inv2a, cx, cy, cz);
+        ct[3 * t + 1] = cx * gx + cy * gy + cz * gz;
+        corner_curl(g, a, b, inv2a, cx, cy, cz);
+        ct[3 * t + 2] = cx * gx + cy * gy + cz * gz;
+    }
+}
+
+__global__ __launch_bounds__(KT) void k_curl_t(GeoDev g, int64_t nv, const double *__restrict__ ct, double alpha,
+                                               double *__restrict__ y)
 {
     for (int64_t j = blockIdx.x * (int64_t)KT + threadIdx.x; j < nv; j += (int64_t)gridDim.x * KT) {
         double s = 0.0;
         for (int64_t e = g.vt_ptr[j]; e < g.vt_ptr[j + 1]; ++e) {
             const int32_t t = g.vt_idx[e];
-            const int32_t a = g.t0[t], b = g.t1[t], d = g.t2[t];
-            const int32_t nxt = j == a ? b : j == b ? d : a;
-            const int32_t prv = j == a ? d : j == b ? a : b;
-            double cx, cy, cz;
-            corner_curl(g, nxt, prv, 1.0 / (2.0 * tri_area(g, t)), cx, cy, cz);
-            s += cx * gc[t] + cy * gc[t + nt] + cz * gc[t + 2 * nt];
+            const int corner = j == g.t0[t] ? 0 : j == g.t1[t] ? 1 : 2;
+            s += ct[3 * (int64_t)t + corner];
         }
         y[j] += alpha * s;
     }
@@ -468,7 +483,9 @@ void hypersingular_matvec(Op &G, double alpha, const double *x, double *y, hipSt
     // the row-panel kernels, while one three-column block product pads to the
     // 16-column matrix-core tiles (13.1 ms against 3 x 2.6 ms at 2M triangles)
     for (int d = 0; d < 3; ++d) matvec(G, 0, 1.0, c + d * nt, nt, gc + d * nt, nt, 1, st);
-    hipLaunchKernelGGL(k_curl_t, dim3(grid_for(nv)), dim3(KT), 0, st, G.geo, nv, nt, gc, alpha, y);
+    // the curls are consumed by now: their buffer takes the corner contributions
+    hipLaunchKernelGGL(k_curl_corners, dim3(grid_for(nt)), dim3(KT), 0, st, G.geo, nt, gc, c);
+    hipLaunchKernelGGL(k_curl_t, dim3(grid_for(nv)), dim3(KT), 0, st, G.geo, nv, c, alpha, y);
     hip_check(hipGetLastError(), "curl transpose launch");
 }
 
