@@ -111,6 +111,19 @@ h2b_status h2b_tree_info(h2b_tree tree, int64_t *n, int64_t *nclusters, int64_t 
 h2b_status h2b_tree_arrays(h2b_tree tree, int32_t *perm, int32_t *begin, int32_t *end,
                            int32_t *parent, double *box);
 
+/* Green cross approximation of a tree's cluster bases (Section 4; see
+ * h2b_params.gca_tol): the cross approximation of every cluster, bottom-up,
+ * on the host only (no device work).  order_m: Gauss points per direction on
+ * each face of the auxiliary box (1..6); eps > 0: tolerance relative to the
+ * first pivot.  ranks[nclusters] receives k_t per cluster (pre-order ids);
+ * pivots, if not NULL, receives the pivot indices (original triangle or
+ * vertex indices) cluster after cluster in pivot order, at most
+ * sum_t min(|t|, 12 m^2) entries (npivots receives the number written).
+ * The operators built with gca_tol use the same construction.
+ * Errors: H2B_EINVAL for a NULL tree or ranks, order_m outside 1..6, eps <= 0. */
+h2b_status h2b_tree_gca(h2b_tree tree, int order_m, double eps, int32_t *ranks, int32_t *pivots,
+                        int64_t *npivots);
+
 /* ----------------------------------------------------------------- blocks */
 
 /* Block tree (Section 2, Definition "Block tree") of rows x cols with the

@@ -82,6 +82,7 @@ _SIGS = {
     "h2b_tree_destroy": ([_vp], ctypes.c_int),
     "h2b_tree_info": ([_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)], ctypes.c_int),
     "h2b_tree_arrays": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_tree_gca": ([_vp, ctypes.c_int, _dbl, _vp, _vp, _P(_i64)], ctypes.c_int),
     "h2b_blocks_build": ([_vp, _vp, _dbl, ctypes.c_int, _P(_vp)], ctypes.c_int),
     "h2b_blocks_destroy": ([_vp], ctypes.c_int),
     "h2b_blocks_info": ([_vp, _P(_i64), _P(_i64), _P(_i64)], ctypes.c_int),
@@ -169,6 +170,17 @@ class Tree:
         box = np.zeros((self.nclusters, 6))
         _check(h2b_tree_arrays(self.handle, _ptr(perm), _ptr(b), _ptr(e), _ptr(par), _ptr(box)))
         return dict(perm=perm, begin=b, end=e, parent=par, box=box)
+
+    def gca(self, order_m, eps):
+        """Ranks (per cluster) and pivot lists of the Green cross
+        approximation of this tree's bases, computed on the host."""
+        ranks = np.zeros(self.nclusters, dtype=np.int32)
+        piv = np.zeros(self.n * 2 + 12 * order_m * order_m * self.nclusters, dtype=np.int32)
+        npiv = _i64()
+        _check(h2b_tree_gca(self.handle, int(order_m), float(eps), _ptr(ranks), _ptr(piv), ctypes.byref(npiv)))
+        piv = piv[:npiv.value]
+        offs = np.concatenate([[0], np.cumsum(ranks)])
+        return ranks, [piv[offs[c]:offs[c + 1]] for c in range(self.nclusters)]
 
     def __del__(self, _destroy=h2b_tree_destroy):
         if getattr(self, "handle", None):

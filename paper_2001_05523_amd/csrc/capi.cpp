@@ -2,6 +2,7 @@
 // translation of internal errors into h2b_status codes.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -118,6 +119,25 @@ h2b_status h2b_tree_arrays(h2b_tree tree, int32_t *perm, int32_t *begin, int32_t
         if (end) std::memcpy(end, T.end.data(), sizeof(int32_t) * T.end.size());
         if (parent) std::memcpy(parent, T.parent.data(), sizeof(int32_t) * T.parent.size());
         if (box) std::memcpy(box, T.box.data(), sizeof(double) * T.box.size());
+    });
+}
+
+h2b_status h2b_tree_gca(h2b_tree tree, int order_m, double eps, int32_t *ranks, int32_t *pivots,
+                        int64_t *npivots)
+{
+    return guarded([&] {
+        need(tree, "tree");
+        need(ranks, "ranks");
+        if (order_m < 1 || order_m > h2b::MMAX) h2b::fail(H2B_EINVAL, "order_m must be in 1..6");
+        if (!(eps > 0.0) || !std::isfinite(eps)) h2b::fail(H2B_EINVAL, "eps must be finite and > 0");
+        const h2b::GcaBases G = h2b::gca_bases(*tree->t, order_m, eps);
+        int64_t k = 0;
+        for (size_t c = 0; c < G.rank.size(); ++c) {
+            ranks[c] = G.rank[c];
+            if (pivots)
+                for (int32_t p : G.hat[c]) pivots[k++] = p;
+        }
+        if (npivots) *npivots = k;
     });
 }
 

@@ -127,3 +127,28 @@ def test_null_arguments_rejected():
     assert h.h2b_tree_build(None, 0, 4, ctypes.byref(out)) == h.H2B_EINVAL
     assert b"NULL" in h.h2b_last_error()
     assert h.h2b_matvec(None, 0, 1.0, None, 1, None, 1, 1, None) == h.H2B_EINVAL
+
+
+@pytest.mark.parametrize("space", [0, 1])
+@pytest.mark.parametrize("m,eps", [(2, 1e-2), (3, 1e-4)])
+def test_gca_pivots_equal_oracle(space, m, eps):
+    """The library's host construction of the Green cross approximation picks
+    the oracle's ranks and pivots cluster by cluster (perturbed sphere: no
+    mirror symmetries, so no ties), for triangle clusters and for the vertex
+    clusters of K's columns."""
+    from oracle import gca, h2
+    h = _lib()
+    v, t = synth.perturbed_sphere(4, seed=3)
+    mesh = h.Mesh(v, t)
+    tree = h.Tree(mesh, space, 8)
+    ranks, piv = tree.gca(m, eps)
+    pts = v[t].mean(axis=1) if space == 0 else v
+    root, perm, clusters = h2.cluster_tree(pts, 8)
+    h2.support_boxes(clusters, v, t, "P0" if space == 0 else "P1")
+    hat, _ = gca.gca_bases(v, t, clusters, perm, m, eps, space="P0" if space == 0 else "P1")
+    assert len(clusters) == len(ranks)
+    for c in clusters:
+        assert ranks[c.id] == len(hat[c.id]), c.id
+        assert np.array_equal(piv[c.id], hat[c.id]), c.id
+    with pytest.raises(h.H2BError):
+        tree.gca(0, eps)
