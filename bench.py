@@ -371,7 +371,47 @@ def gca_solve(torch, h2b, mesh, verts, tris, args):
     res["l2_error_neumann"] = neumann_l2_error_u1(verts, tris, t.cpu().numpy())
     log("GCA DtN solve: %d iterations, %.1f ms, L2 error %.4e" % (r["iterations"], r["solve_ms"],
                                                                  res["l2_error_neumann"]))
+    # Neumann-to-Dirichlet with W from the GCA G and the right-hand side from the GCA K
+    a, b3, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    cr = np.cross(b3 - a, c - a)
+    n = cr / np.linalg.norm(cr, axis=1)[:, None]
+    cen = (a + b3 + c) / 3.0
+    tn = torch.tensor(2.0 * cen[:, 0] * n[:, 0] - 2.0 * cen[:, 2] * n[:, 2], dtype=torch.float64, device="cuda")
+    rhs = h2b.ntd_rhs(gops["K"], tn)
+    uh = torch.zeros_like(rhs)
+    r = G.cg(rhs, uh, tol=1e-10, max_iter=3000, form="hypersingular")
+    res["ntd"] = {"iterations": r["iterations"], "status": r["status"], "solve_ms": round(r["solve_ms"], 1),
+                  "rel_residual": r["rel_residual"],
+                  "l2_error_dirichlet": dirichlet_l2_error_u1(verts, tris, uh.cpu().numpy())}
+    log("GCA NtD solve: %d iterations, %.1f ms, L2 error of the Dirichlet data %.4e" % (
+        r["iterations"], r["solve_ms"], res["ntd"]["l2_error_dirichlet"]))
     return res
+
+
+def dirichlet_l2_error_u1(verts, tris, uh):
+    """|| (u_h - mean) - (u1 - mean) ||_L2 for the P1 function u_h against
+    u1 = x1^2 - x3^2 on the flat triangles (collapsed 4 x 4 Gauss rule, exact
+    for the quartic integrand; both sides with zero mean, since the Neumann
+    data fix u only up to a constant)."""
+    z, w = np.polynomial.legendre.leggauss(4)
+    t1, w1 = 0.5 * (z + 1.0), 0.5 * w
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    jac = np.linalg.norm(np.cross(b - a, c - b), axis=1)
+    num = den = 0.0
+    vals, wts = [], []
+    for i in range(4):
+        for j in range(4):
+            u1, u2 = t1[i], t1[i] * t1[j]
+            x = a + u1 * (b - a) + u2 * (c - b)
+            lam = (1.0 - u1, u1 - u2, u2)
+            vh = lam[0] * uh[tris[:, 0]] + lam[1] * uh[tris[:, 1]] + lam[2] * uh[tris[:, 2]]
+            vals.append((vh, x[:, 0] ** 2 - x[:, 2] ** 2))
+            wts.append(w1[i] * w1[j] * t1[i] * jac)
+    tot = sum(wt.sum() for wt in wts)
+    mh = sum((wt * vh).sum() for (vh, _), wt in zip(vals, wts)) / tot
+    mu = sum((wt * vu).sum() for (_, vu), wt in zip(vals, wts)) / tot
+    err2 = sum((wt * ((vh - mh) - (vu - mu)) ** 2).sum() for (vh, vu), wt in zip(vals, wts))
+    return float(np.sqrt(err2))
 
 
 def synth_vector(n):
