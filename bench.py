@@ -433,8 +433,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
-    ap.add_argument("--gca-solve", action="store_true",
-                    help="also solve the Dirichlet-to-Neumann system with GCA operators (minutes of setup)")
+    ap.add_argument("--no-gca-solve", action="store_true",
+                    help="skip the solves with GCA operators (about a minute of setup)")
     ap.add_argument("--gca-order", type=int, default=4)
     ap.add_argument("--gca-tol", type=float, default=1e-6)
     ap.add_argument("--no-solve", action="store_true",
@@ -648,12 +648,16 @@ def main():
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))
 
-    if args.gca_solve:
+    if not args.no_gca_solve:
         # the benchmark operators make room for the GCA pair
         dop = None
         ops.clear()
         torch.cuda.empty_cache()
-        out["gca_solve"] = gca_solve(torch, h2b, mesh, verts, tris, args)
+        try:
+            out["gca_solve"] = gca_solve(torch, h2b, mesh, verts, tris, args)
+        except (h2b.H2BError, RuntimeError, MemoryError) as e:
+            out["gca_solve"] = {"error": str(e)}
+            log("GCA solves failed: %s" % e)
 
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
