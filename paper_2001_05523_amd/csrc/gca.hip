@@ -25,6 +25,7 @@
 // (and pivot vertices for K's columns).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -108,47 +109,77 @@ void green_matrix(const Mesh &M, const std::vector<int32_t> &rows, const FaceRul
 }
 
 // L = [B D] for the vertices `rows` (hat functions on the triangles around
-// each vertex, normal derivatives in y).
+// each vertex, normal derivatives in y).  Every triangle around the rows is
+// integrated once; its kernel values at the quadrature points go to each of
+// its corners that is a row, weighted by that corner's barycentric
+// coordinate.  Rows accumulate their triangles in increasing index order.
 void green_matrix_p1(const Mesh &M, const std::vector<int32_t> &rows, const FaceRule &F,
                      const std::vector<double> &tq, const std::vector<double> &wq, std::vector<double> &L)
 {
-    const int k = F.k, q = (int)tq.size();
+    const int k = F.k, q = (int)tq.size(), nq = q * q;
     L.assign(rows.size() * 2 * (size_t)k, 0.0);
-    for (size_t r = 0; r < rows.size(); ++r) {
-        const int j = rows[r];
-        double *row = &L[r * 2 * (size_t)k];
-        for (int64_t e = M.vt_ptr[j]; e < M.vt_ptr[j + 1]; ++e) {
-            const int i = M.vt_idx[e];
-            const int a = M.t0[i], b = M.t1[i], c = M.t2[i];
-            const int corner = j == a ? 0 : j == b ? 1 : 2;
-            const double P0[3] = {M.vx[a], M.vy[a], M.vz[a]}, P1[3] = {M.vx[b], M.vy[b], M.vz[b]},
-                         P2[3] = {M.vx[c], M.vy[c], M.vz[c]};
-            double e1[3], e2[3];
-            for (int d = 0; d < 3; ++d) e1[d] = P1[d] - P0[d], e2[d] = P2[d] - P1[d];
-            const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
-                         cz = e1[0] * e2[1] - e1[1] * e2[0];
-            const double jac = std::sqrt(cx * cx + cy * cy + cz * cz);
-            const double ny[3] = {cx / jac, cy / jac, cz / jac};
-            for (int qa = 0; qa < q; ++qa)
-                for (int qb = 0; qb < q; ++qb) {
-                    const double u1 = tq[qa], u2 = tq[qa] * tq[qb];
-                    const double lam = corner == 0 ? 1.0 - u1 : corner == 1 ? u1 - u2 : u2;
-                    const double wt = wq[qa] * wq[qb] * tq[qa] * jac * lam;
-                    double y[3];
-                    for (int d = 0; d < 3; ++d) y[d] = P0[d] + u1 * e1[d] + u2 * e2[d];
-                    for (int nu = 0; nu < k; ++nu) {
-                        const double dx = y[0] - F.z[3 * nu], dy = y[1] - F.z[3 * nu + 1], dz = y[2] - F.z[3 * nu + 2];
-                        const double r2 = dx * dx + dy * dy + dz * dz, rr = std::sqrt(r2);
-                        const double g3 = 1.0 / (FOUR_PI * rr * r2);  // 1 / (4 pi r^3)
-                        const double dny = dx * ny[0] + dy * ny[1] + dz * ny[2];
-                        const double* n = &F.n[3 * nu];
-                        const double dnz = dx * n[0] + dy * n[1] + dz * n[2];
-                        const double nn = ny[0] * n[0] + ny[1] * n[1] + ny[2] * n[2];
-                        row[nu] += wt * (-dny * g3);
-                        row[k + nu] += wt * (nn * g3 - 3.0 * dny * dnz * g3 / r2);
-                    }
+    std::vector<std::pair<int32_t, int32_t>> vr(rows.size());
+    for (size_t r = 0; r < rows.size(); ++r) vr[r] = {rows[r], (int32_t)r};
+    std::sort(vr.begin(), vr.end());
+    auto row_of = [&](int32_t v) {
+        auto it = std::lower_bound(vr.begin(), vr.end(), std::make_pair(v, (int32_t)-1));
+        return it != vr.end() && it->first == v ? it->second : -1;
+    };
+    std::vector<int32_t> tris;
+    for (int32_t v : rows)
+        for (int64_t e = M.vt_ptr[v]; e < M.vt_ptr[v + 1]; ++e) tris.push_back(M.vt_idx[e]);
+    std::sort(tris.begin(), tris.end());
+    tris.erase(std::unique(tris.begin(), tris.end()), tris.end());
+    std::vector<double> kb((size_t)nq * k), kd((size_t)nq * k), wp(nq), lam(3 * (size_t)nq);
+    for (int32_t i : tris) {
+        const int a = M.t0[i], b = M.t1[i], c = M.t2[i];
+        const double P0[3] = {M.vx[a], M.vy[a], M.vz[a]}, P1[3] = {M.vx[b], M.vy[b], M.vz[b]},
+                     P2[3] = {M.vx[c], M.vy[c], M.vz[c]};
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) e1[d] = P1[d] - P0[d], e2[d] = P2[d] - P1[d];
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                     cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double jac = std::sqrt(cx * cx + cy * cy + cz * cz);
+        const double ny[3] = {cx / jac, cy / jac, cz / jac};
+        for (int qa = 0; qa < q; ++qa)
+            for (int qb = 0; qb < q; ++qb) {
+                const int pt = qa * q + qb;
+                const double u1 = tq[qa], u2 = tq[qa] * tq[qb];
+                wp[pt] = wq[qa] * wq[qb] * tq[qa] * jac;
+                lam[3 * pt] = 1.0 - u1;
+                lam[3 * pt + 1] = u1 - u2;
+                lam[3 * pt + 2] = u2;
+                double y[3];
+                for (int d = 0; d < 3; ++d) y[d] = P0[d] + u1 * e1[d] + u2 * e2[d];
+                for (int nu = 0; nu < k; ++nu) {
+                    const double dx = y[0] - F.z[3 * nu], dy = y[1] - F.z[3 * nu + 1], dz = y[2] - F.z[3 * nu + 2];
+                    const double r2 = dx * dx + dy * dy + dz * dz, rr = std::sqrt(r2);
+                    const double g3 = 1.0 / (FOUR_PI * rr * r2);  // 1 / (4 pi r^3)
+                    const double dny = dx * ny[0] + dy * ny[1] + dz * ny[2];
+                    const double *n = &F.n[3 * nu];
+                    const double dnz = dx * n[0] + dy * n[1] + dz * n[2];
+                    const double nn = ny[0] * n[0] + ny[1] * n[1] + ny[2] * n[2];
+                    kb[(size_t)pt * k + nu] = -dny * g3;
+                    kd[(size_t)pt * k + nu] = nn * g3 - 3.0 * dny * dnz * g3 / r2;
                 }
+            }
+        const int corners[3] = {a, b, c};
+        for (int cc = 0; cc < 3; ++cc) {
+            const int r = row_of(corners[cc]);
+            if (r < 0) continue;
+            double *row = &L[(size_t)r * 2 * k];
+            for (int pt = 0; pt < nq; ++pt) {
+                const double wl = wp[pt] * lam[3 * pt + cc];
+                const double *pb = &kb[(size_t)pt * k], *pd = &kd[(size_t)pt * k];
+                for (int nu = 0; nu < k; ++nu) {
+                    row[nu] += wl * pb[nu];
+                    row[k + nu] += wl * pd[nu];
+                }
+            }
         }
+    }
+    for (size_t r = 0; r < rows.size(); ++r) {
+        double *row = &L[r * 2 * (size_t)k];
         for (int nu = 0; nu < k; ++nu) {
             row[nu] *= F.sw[nu];
             row[k + nu] *= F.sw[nu];
