@@ -263,3 +263,28 @@ def test_ntd_paper_functions_converge_second_order():
         assert e[0] > e[1] > e[2], (name, e)
         rate = math.log2(e[1] / e[2])
         assert 1.7 <= rate <= 2.5, (name, e, rate)
+
+
+def test_error_measures_of_exact_data():
+    """The measuring sticks of the convergence tests: a linear function is its
+    own P1 interpolant, so its Dirichlet L2 error is zero for any added
+    constant, and a constant shift of a P1 function does not change the
+    zero-mean error; the P0 projection of the normal derivative of a linear
+    function is a . n_tau exactly; for u1 the Dirichlet error of the nodal
+    interpolant falls at second order."""
+    v, t = synth.perturbed_sphere(4, seed=9)
+    _, n, _ = _geom(v, t)
+    a = np.array([0.2, -1.1, 0.7])
+    lin = lambda p: p @ a  # noqa: E731
+    assert krylov.dirichlet_l2_error(v, t, v @ a + 5.0, lin) <= 1e-13
+    grad = lambda p: np.broadcast_to(a, p.shape)  # noqa: E731
+    assert np.max(np.abs(krylov.neumann_projection(v, t, grad) - n @ a)) <= 1e-14
+    rng = np.random.default_rng(4)
+    uh = krylov.u1(v) + 0.01 * rng.standard_normal(len(v))
+    e0 = krylov.dirichlet_l2_error(v, t, uh, krylov.u1)
+    assert krylov.dirichlet_l2_error(v, t, uh + 3.0, krylov.u1) == pytest.approx(e0, rel=1e-12)
+    errs = []
+    for s in (4, 8, 16):
+        vs, ts = synth.octa_sphere(s)
+        errs.append(krylov.dirichlet_l2_error(vs, ts, krylov.u1(vs), krylov.u1))
+    assert 1.7 <= math.log2(errs[1] / errs[2]) <= 2.3, errs
