@@ -385,7 +385,8 @@ h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, dou
  * iterate on return; n = rows = columns of A (the number of vertices for the
  * hypersingular form).  history: NULL, or a host array
  * of max_iter + 1 doubles receiving ||r_k|| / ||b|| for k = 0..iterations.
- * Work vectors (3 n doubles plus small state) are allocated per call.  The
+ * Work vectors (3 n doubles, one more with the preconditioner and two more
+ * for the hypersingular form, plus small state) are allocated per call.  The
  * call synchronises hip_stream and returns when the solve has ended.
  * precond = H2B_PRECOND_BLOCK_JACOBI runs preconditioned CG (rho = r^T z,
  * z = P r) with P the block-diagonal matrix of the inverses of the symmetric
