@@ -152,3 +152,14 @@ def test_gca_pivots_equal_oracle(space, m, eps):
         assert np.array_equal(piv[c.id], hat[c.id]), c.id
     with pytest.raises(h.H2BError):
         tree.gca(0, eps)
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py measures one MI355X: a request for several GPUs exits with a
+    message before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
