@@ -47,6 +47,8 @@ def lib():
         L.orc_dlp_dense.argtypes = [i64, vp, i64, vp, i32, vp]
         L.orc_slp_rows.argtypes = [i64, vp, i64, vp, i32, i32, i64, vp, vp, vp]
         L.orc_dlp_rows.argtypes = [i64, vp, i64, vp, i32, i32, i64, vp, vp, vp]
+        L.orc_slp_block.argtypes = [i64, vp, i64, vp, i32, i64, vp, i64, vp, vp]
+        L.orc_dlp_block.argtypes = [i64, vp, i64, vp, i32, i64, vp, i64, vp, vp]
         L.orc_slp_entry.argtypes = [i64, vp, i64, vp, i32, i64, i64]
         L.orc_slp_entry.restype = dbl
         L.orc_dlp_pair.argtypes = [i64, vp, i64, vp, i32, i64, i64, vp]
@@ -120,6 +122,30 @@ def dlp_rows(verts, tris, q, rows, x, trans=False):
                           len(rows), _ptr(rows), _ptr(x), _ptr(y)) != 0:
         raise ValueError("bad quadrature order")
     return y
+
+
+def slp_block(verts, tris, q, rows, cols):
+    """Dense G entries G[rows][:, cols] (rows and columns are triangles)."""
+    V, T = _mesh(verts, tris)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros((len(rows), len(cols)))
+    if lib().orc_slp_block(len(V), _ptr(V), len(T), _ptr(T), q, len(rows), _ptr(rows), len(cols),
+                           _ptr(cols), _ptr(out)) != 0:
+        raise ValueError("bad quadrature order or index")
+    return out
+
+
+def dlp_block(verts, tris, q, rows, cols):
+    """Dense K entries K[rows][:, cols] (rows triangles, columns vertices)."""
+    V, T = _mesh(verts, tris)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros((len(rows), len(cols)))
+    if lib().orc_dlp_block(len(V), _ptr(V), len(T), _ptr(T), q, len(rows), _ptr(rows), len(cols),
+                           _ptr(cols), _ptr(out)) != 0:
+        raise ValueError("bad quadrature order or index")
+    return out
 
 
 def slp_entry(verts, tris, q, i, j):

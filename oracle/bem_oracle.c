@@ -493,3 +493,74 @@ int orc_dlp_pair(int64_t nv, const double *V, int64_t nt, const int32_t *T, int 
     dlp_pair(&m, i, j, val);
     return 0;
 }
+
+/* Entries of the dense matrices at given rows and columns (row-major
+ * nr x nc): out[a][b] = G[rows[a], cols[b]] (cols are triangles), or
+ * K[rows[a], cols[b]] (cols are vertices; K_ij sums the slot of vertex j over
+ * the pairs (i, tau) of the triangles tau around j, in increasing order of
+ * tau, as the dense K does). */
+int orc_slp_block(int64_t nv, const double *V, int64_t nt, const int32_t *T, int q,
+                  int64_t nr, const int64_t *rows, int64_t nc, const int64_t *cols,
+                  double *out)
+{
+    orc_mesh m;
+    if (mesh_init(&m, nv, V, nt, T, q)) return -1;
+    for (int64_t a = 0; a < nr; ++a)
+        if (rows[a] < 0 || rows[a] >= nt) return -1;
+    for (int64_t b = 0; b < nc; ++b)
+        if (cols[b] < 0 || cols[b] >= nt) return -1;
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int64_t a = 0; a < nr; ++a)
+        for (int64_t b = 0; b < nc; ++b)
+            out[a * nc + b] = slp_entry(&m, rows[a], cols[b]);
+    return 0;
+}
+
+int orc_dlp_block(int64_t nv, const double *V, int64_t nt, const int32_t *T, int q,
+                  int64_t nr, const int64_t *rows, int64_t nc, const int64_t *cols,
+                  double *out)
+{
+    orc_mesh m;
+    if (mesh_init(&m, nv, V, nt, T, q)) return -1;
+    for (int64_t a = 0; a < nr; ++a)
+        if (rows[a] < 0 || rows[a] >= nt) return -1;
+    for (int64_t b = 0; b < nc; ++b)
+        if (cols[b] < 0 || cols[b] >= nv) return -1;
+    /* triangles around each vertex, in increasing triangle order */
+    int64_t *ptr = calloc((size_t)nv + 1, sizeof(int64_t));
+    int64_t *adj = malloc(sizeof(int64_t) * (size_t)(3 * nt));
+    if (!ptr || !adj) {
+        free(ptr);
+        free(adj);
+        return -2;
+    }
+    for (int64_t j = 0; j < 3 * nt; ++j) ptr[T[j] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) ptr[v + 1] += ptr[v];
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)nv);
+    if (!fill) {
+        free(ptr);
+        free(adj);
+        return -2;
+    }
+    for (int64_t v = 0; v < nv; ++v) fill[v] = ptr[v];
+    for (int64_t j = 0; j < nt; ++j)
+        for (int c = 0; c < 3; ++c) adj[fill[T[3 * j + c]]++] = j;
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int64_t a = 0; a < nr; ++a)
+        for (int64_t b = 0; b < nc; ++b) {
+            const int64_t vtx = cols[b];
+            double s = 0.0;
+            for (int64_t e = ptr[vtx]; e < ptr[vtx + 1]; ++e) {
+                const int64_t tau = adj[e];
+                double val[3];
+                dlp_pair(&m, rows[a], tau, val);
+                for (int c = 0; c < 3; ++c)
+                    if (T[3 * tau + c] == vtx) s += val[c];
+            }
+            out[a * nc + b] = s;
+        }
+    free(fill);
+    free(ptr);
+    free(adj);
+    return 0;
+}

@@ -343,3 +343,150 @@ def h2_dense(verts, tris, kernel, leaf, m, eta=1.0, q_near=4, q_basis=None,
                 far_blocks=[(t.id, s.id) for t, s in far],
                 near_blocks=[(t.id, s.id) for t, s in near])
     return A, info
+
+
+# ------------------------------------------- sampled rows of the H^2 matrix
+#
+# For meshes whose dense H^2 matrix is too large to write out, the rows of
+# A X for a few row indices: the same trees, block tree, interpolation bases,
+# couplings and near-field entries as h2_dense, summed block by block for
+# each requested row without forming A.
+
+def _tensor_quad(wq, a, b, c):
+    """Quadrature of tensor products: out[n, nu] = sum_q wq[n, q] a[n, q, n1]
+    b[n, q, n2] c[n, q, n3] with nu = n1 + m n2 + m^2 n3 (one batched matrix
+    product over q per row n)."""
+    n, Q, m = a.shape
+    B = wq[:, :, None, None] * c[:, :, :, None] * b[:, :, None, :]
+    return np.matmul(B.reshape(n, Q, m * m).transpose(0, 2, 1), a).reshape(n, m ** 3)
+
+
+def _factors(axes, X, f):
+    """f(axes[d], X[..., d]) per axis, shaped like X[..., 0] plus one axis."""
+    return [f(axes[d], X[..., d].ravel()).reshape(X.shape[:-1] + (len(axes[d]),)) for d in range(3)]
+
+
+def basis_p0_many(verts, tris, idx, axes, q, chunk=2048):
+    """(V_t)_{i nu} = int_{tau_i} L_{t,nu} for many triangles at once (the
+    same collapsed rule as basis_p0)."""
+    U, W = triangle_rule(q)
+    idx = np.asarray(idx, dtype=np.int64)
+    out = np.zeros((len(idx), len(axes[0]) ** 3))
+    for c0 in range(0, len(idx), chunk):
+        tr = tris[idx[c0:c0 + chunk]]
+        P0, P1, P2 = verts[tr[:, 0]], verts[tr[:, 1]], verts[tr[:, 2]]
+        X = P0[:, None, :] + U[None, :, :1] * (P1 - P0)[:, None, :] + U[None, :, 1:2] * (P2 - P1)[:, None, :]
+        J = np.linalg.norm(np.cross(P1 - P0, P2 - P1), axis=1)
+        l = _factors(axes, X, lagrange_1d)
+        out[c0:c0 + len(tr)] = J[:, None] * _tensor_quad(np.broadcast_to(W, (len(tr), len(W))), *l)
+    return out
+
+
+def basis_p1_nd_many(verts, tris, adj, idx, axes, q):
+    """(W_s)_{j mu} = sum_{tau around j} int_tau phi_j <grad L_{s,mu}, n_tau>
+    for many vertices at once (the same rule as basis_p1_normal_derivative)."""
+    inc_row, inc_tri, inc_slot = [], [], []
+    for r, j in enumerate(idx):
+        for k in adj[j]:
+            inc_row.append(r)
+            inc_tri.append(k)
+            inc_slot.append(list(tris[k]).index(j))
+    return _basis_p1_nd_incidences(verts, tris, len(idx), np.asarray(inc_row, dtype=np.int64),
+                                   np.asarray(inc_tri, dtype=np.int64), np.asarray(inc_slot, dtype=np.int64),
+                                   axes, q)
+
+
+def _basis_p1_nd_incidences(verts, tris, nrows, inc_row, inc_tri, inc_slot, axes, q, chunk=1024):
+    """Sum over incidences (row r, triangle tau, corner slot c of the row's
+    vertex in tau) of int_tau lambda_c <grad L_mu, n_tau> into row r."""
+    U, W = triangle_rule(q)
+    lam = np.stack([1.0 - U[:, 0], U[:, 0] - U[:, 1], U[:, 1]], axis=1)
+    m = len(axes[0])
+    out = np.zeros((nrows, m ** 3))
+    for c0 in range(0, len(inc_row), chunk):
+        tr = tris[inc_tri[c0:c0 + chunk]]
+        P0, P1, P2 = verts[tr[:, 0]], verts[tr[:, 1]], verts[tr[:, 2]]
+        X = P0[:, None, :] + U[None, :, :1] * (P1 - P0)[:, None, :] + U[None, :, 1:2] * (P2 - P1)[:, None, :]
+        J = np.linalg.norm(np.cross(P1 - P0, P2 - P1), axis=1)
+        nrm = np.cross(P1 - P0, P2 - P0)
+        nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+        l = _factors(axes, X, lagrange_1d)
+        dl = _factors(axes, X, lagrange_1d_deriv)
+        wl = W[None, :] * lam[:, inc_slot[c0:c0 + chunk]].T
+        dn = (_tensor_quad(wl * nrm[:, :1], dl[0], l[1], l[2]) + _tensor_quad(wl * nrm[:, 1:2], l[0], dl[1], l[2])
+              + _tensor_quad(wl * nrm[:, 2:3], l[0], l[1], dl[2]))
+        np.add.at(out, inc_row[c0:c0 + chunk], J[:, None] * dn)
+    return out
+
+
+def h2_rows(verts, tris, kernel, leaf, m, rows, X, eta=1.0, q_near=4, q_basis=None):
+    """Rows ``rows`` of A X for the H^2 matrix A that h2_dense writes out
+    (kernel 'slp' or 'dlp'); X has one row per column of A (vector or
+    matrix).  Row i gets, from each nearfield leaf (t_i, s) of its leaf
+    cluster t_i, the dense entries times X|_s, and from each farfield block
+    (t, s) whose row cluster t contains i, V_t[i] S_ts (W_s^T X|_s)."""
+    from . import slp_block, dlp_block
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    X = np.asarray(X, dtype=np.float64)
+    vec = X.ndim == 1
+    X2 = X[:, None] if vec else X
+    if q_basis is None:
+        q_basis = 2 * m + 1
+    cent = verts[tris].mean(axis=1)
+    rt, rperm, rcl = cluster_tree(cent, leaf)
+    support_boxes(rcl, verts, tris, "P0")
+    if kernel == "slp":
+        ct, cperm, ccl = rt, rperm, rcl
+    else:
+        ct, cperm, ccl = cluster_tree(verts, leaf)
+        support_boxes(ccl, verts, tris, "P1")
+    far, near = block_tree(rt, ct, eta)
+    far_by_t, near_by_t = {}, {}
+    for t, s in far:
+        far_by_t.setdefault(t.id, []).append(s)
+    for t, s in near:
+        near_by_t.setdefault(t.id, []).append(s)
+    if kernel == "dlp":
+        # corner incidences (triangle, slot) sorted by their vertex's position
+        # in the column cluster order: each vertex cluster owns one range
+        cpos = np.empty(len(cperm), dtype=np.int64)
+        cpos[cperm] = np.arange(len(cperm))
+        key = cpos[tris.ravel()]
+        order = np.argsort(key, kind="stable")
+        inc_pos, inc_tri, inc_slot = key[order], order // 3, order % 3
+    pos = np.empty(len(rperm), dtype=np.int64)
+    pos[rperm] = np.arange(len(rperm))
+    xhat = {}
+    out = np.zeros((len(rows), X2.shape[1]))
+    for r, i in enumerate(rows):
+        p = pos[i]
+        c = rt
+        path = [c]
+        while c.children:
+            c = next(ch for ch in c.children if ch.begin <= p < ch.end)
+            path.append(c)
+        for t in path:
+            if t.id not in far_by_t:
+                continue
+            ax_t = box_axes(t, m)
+            Vi = basis_p0_many(verts, tris, [i], ax_t, q_basis)[0]
+            for s in far_by_t[t.id]:
+                if s.id not in xhat:
+                    ax_s = box_axes(s, m)
+                    cols = cperm[s.begin:s.end]
+                    if kernel == "slp":
+                        Ws = basis_p0_many(verts, tris, cols, ax_s, q_basis)
+                    else:
+                        a, b = np.searchsorted(inc_pos, [s.begin, s.end])
+                        Ws = _basis_p1_nd_incidences(verts, tris, s.end - s.begin, inc_pos[a:b] - s.begin,
+                                                     inc_tri[a:b], inc_slot[a:b], ax_s, q_basis)
+                    xhat[s.id] = Ws.T @ X2[cols]
+                out[r] += Vi @ coupling(ax_t, box_axes(s, m)) @ xhat[s.id]
+        leaf_t = path[-1]
+        cols = np.concatenate([cperm[s.begin:s.end] for s in near_by_t.get(leaf_t.id, [])] or
+                              [np.zeros(0, dtype=np.int64)])
+        if len(cols):
+            ent = (slp_block if kernel == "slp" else dlp_block)(verts, tris, q_near, [i], cols)
+            out[r] += ent[0] @ X2[cols]
+    return out[:, 0] if vec else out

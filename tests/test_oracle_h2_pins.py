@@ -166,3 +166,75 @@ def test_interpolation_error_decays_geometrically():
     ratios = [errs[i + 1] / errs[i] for i in range(3)]
     assert all(0.02 < r < 0.3 for r in ratios), (errs, ratios)
     assert info["far"] > 0
+
+
+# ----------------------------------------- sampled rows of the H^2 product
+
+def test_dense_blocks_equal_dense_matrices():
+    """Dense entries at chosen rows and columns equal the pinned dense G and K
+    (Section 1, eqs. (slp), (dlp)); for K every vertex valence of the mesh is
+    among the columns."""
+    v, t = synth.perturbed_sphere(4, 401)
+    G = oracle.slp_dense(v, t, 4)
+    K = oracle.dlp_dense(v, t, 4)
+    r = np.array([0, 9, 64, 127])
+    c = np.array([5, 0, 127, 64, 64])
+    np.testing.assert_allclose(oracle.slp_block(v, t, 4, r, c), G[np.ix_(r, c)], rtol=1e-15, atol=0)
+    val = np.bincount(t.ravel(), minlength=len(v))
+    cv = np.unique(np.concatenate([[0, len(v) - 1], [np.flatnonzero(val == d)[0] for d in np.unique(val)]]))
+    np.testing.assert_allclose(oracle.dlp_block(v, t, 4, r, cv), K[np.ix_(r, cv)], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_vectorised_bases_equal_per_triangle_bases(m):
+    """The many-triangle forms of the leaf bases (Section 3: integrals of the
+    Lagrange polynomials; Section 5: their normal derivatives against the hat
+    functions) equal the per-triangle forms."""
+    v, t = synth.perturbed_sphere(4, 401)
+    cent = v[t].mean(axis=1)
+    _, _, cl = h2.cluster_tree(cent, 16)
+    h2.support_boxes(cl, v, t, "P0")
+    c = cl[3]
+    ax = h2.box_axes(c, m)
+    idx = np.arange(len(t))[::7]
+    np.testing.assert_allclose(h2.basis_p0_many(v, t, idx, ax, 2 * m + 1), h2.basis_p0(v, t, idx, ax, 2 * m + 1),
+                               rtol=1e-13, atol=1e-16)
+    adj = [[] for _ in range(len(v))]
+    for k, tr in enumerate(t):
+        for vv in tr:
+            adj[vv].append(k)
+    vidx = np.arange(len(v))[::5]
+    np.testing.assert_allclose(h2.basis_p1_nd_many(v, t, adj, vidx, ax, 2 * m + 1),
+                               h2.basis_p1_normal_derivative(v, t, adj, vidx, ax, 2 * m + 1),
+                               rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_h2_rows_equal_dense_h2(kernel):
+    """Sampled rows of A X, summed block by block, equal the same rows of the
+    written-out H^2 matrix times X (several right-hand sides)."""
+    v, t = synth.perturbed_sphere(8, 401)
+    A, _ = h2.h2_dense(v, t, kernel, 16, 3)
+    X = synth.random_vector(A.shape[1], 6, cols=4).reshape(A.shape[1], 4)
+    rows = [0, 13, 255, 300, len(t) - 1]
+    Y = h2.h2_rows(v, t, kernel, 16, 3, rows, X)
+    ref = A[rows] @ X
+    assert np.max(np.abs(Y - ref)) <= 1e-14 * np.max(np.abs(ref))
+    y1 = h2.h2_rows(v, t, kernel, 16, 3, rows, X[:, 2])
+    assert np.max(np.abs(y1 - ref[:, 2])) <= 1e-14 * np.max(np.abs(ref[:, 2]))
+
+
+@pytest.mark.parametrize("kernel,m", [("slp", 3), ("dlp", 3), ("slp", 4), ("dlp", 4)])
+def test_basis_rule_exact_from_degree(kernel, m):
+    """On a flat triangle L_nu is a polynomial of total degree 3(m-1) in the
+    reference coordinates (and so is phi_j times a derivative of L_nu), and
+    the collapsed q-point rule integrates degree d exactly for
+    q >= (d + 2)/2.  So q = (3(m-1) + 3) // 2 gives the same rows as the
+    default 2m + 1 points."""
+    v, t = synth.perturbed_sphere(8, 401)
+    ncol = len(t) if kernel == "slp" else len(v)
+    x = synth.random_vector(ncol, 7)
+    rows = [3, 100, 400]
+    a = h2.h2_rows(v, t, kernel, 16, m, rows, x)
+    b = h2.h2_rows(v, t, kernel, 16, m, rows, x, q_basis=(3 * (m - 1) + 3) // 2)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))

@@ -232,3 +232,42 @@ def test_discrete_green_identity_paper_functions_converge():
             r = G @ q0 - (0.5 * _mass(v, t) + K) @ u(v)
             res.append(np.linalg.norm(r) / np.linalg.norm(0.5 * _mass(v, t) @ u(v)))
         assert res[0] > res[1] > res[2], res
+
+
+# ------------------------------------------------ sampled rows of the products
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_slp_rows_equal_dense_matrix(trans):
+    """The sampled rows of G x and G^T x (Section 1, eq. (slp)) that every
+    large-mesh check uses equal rows and columns of the dense matrix, which the
+    pins above tie to closed forms.  A perturbed sphere has no symmetry, so a
+    swapped index (row for column) would show."""
+    v, t = synth.perturbed_sphere(4, 401)
+    G = oracle.slp_dense(v, t, 4)
+    x = synth.random_vector(len(t), 21)
+    rows = np.array([0, 5, 17, 63, 64, 100, len(t) - 1])
+    y = oracle.slp_rows(v, t, 4, rows, x, trans=trans)
+    ref = (G.T if trans else G)[rows] @ x
+    np.testing.assert_allclose(y, ref, rtol=1e-14, atol=1e-14 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_dlp_rows_equal_dense_matrix(trans):
+    """Rows of K x (triangles) and of K^T x (vertices; the pair contributions
+    summed over the triangles around each vertex, Section 1, eq. (dlp)) equal
+    rows and columns of the dense K, pinned by Gauss's identity and the flat
+    plate.  The transposed branch looks up each vertex's corner slot on its own,
+    so it is checked at vertices of every valence the mesh has."""
+    v, t = synth.perturbed_sphere(4, 401)
+    K = oracle.dlp_dense(v, t, 4)
+    x = synth.random_vector(len(t) if trans else len(v), 22)
+    if trans:
+        valence = np.bincount(t.ravel(), minlength=len(v))
+        rows = np.unique(np.concatenate([[0, len(v) - 1],
+                                         [np.flatnonzero(valence == d)[0] for d in np.unique(valence)]]))
+        ref = K[:, rows].T @ x
+    else:
+        rows = np.array([0, 3, 31, 64, 99, len(t) - 1])
+        ref = K[rows] @ x
+    y = oracle.dlp_rows(v, t, 4, rows, x, trans=trans)
+    np.testing.assert_allclose(y, ref, rtol=1e-14, atol=1e-14 * np.max(np.abs(ref)))
