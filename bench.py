@@ -191,7 +191,7 @@ def batching(torch, h2b, synth, reps):
         log("%s x 64 rhs: %.3f ms (coupling %.3f ms, %.1f TFLOP/s on matrix cores)" % (name, ms, ph["coupling"], tf))
         del op, ref
     rng = np.random.default_rng(602)
-    ops, items, ntri = [], [], 0
+    ops, items, ntri, abytes = [], [], 0, 0.0
     for k in range(16):
         s = int(rng.integers(16, 65))
         a, b, c = rng.uniform(0.5, 2.0, size=3)
@@ -206,26 +206,52 @@ def batching(torch, h2b, synth, reps):
         ops.append(op)
         items.append((op, x, y))
         ntri += len(tt)
+        # the merged batch reads the full nearfield of G (not the once-per-pair form)
+        inf = dict(op.info())
+        inf["near_sym_entries"] = 0
+        abytes += alg_bytes(inf, 4)["total"]
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
     batch = h2b.Batch(items)
-    for _ in range(3):
-        batch.launch()
-        for op, x, y in items:
-            op.matvec(x, y)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(2 * reps):
-        batch.launch()
-    torch.cuda.synchronize()
-    bms = (time.perf_counter() - t0) * 1e3 / (2 * reps)
-    t0 = time.perf_counter()
-    for _ in range(2 * reps):
-        for op, x, y in items:
-            op.matvec(x, y)
-    torch.cuda.synchronize()
-    ems = (time.perf_counter() - t0) * 1e3 / (2 * reps)
-    res["batch16"] = {"meshes": 16, "triangles": ntri, "graph_launch_ms": round(bms, 4),
-                      "eager_sequence_ms": round(ems, 4)}
-    log("batch of 16 meshes (%d triangles): one graph launch %.3f ms, eager sequence %.3f ms" % (ntri, bms, ems))
+    bms = timed(batch.launch, 4 * reps)
+    ems = timed(lambda: [op.matvec(x, y) for op, x, y in items], 2 * reps)
+    # reference: one product on the largest mesh of the list alone
+    big = max(range(16), key=lambda i: ops[i].shape[0])
+    bop, bx, by = items[big]
+    inf = bop.info()
+    sms = timed(lambda: bop.matvec(bx, by), 4 * reps)
+    res["batch16"] = {"meshes": 16, "triangles": ntri, "merged": True, "graph_launch_ms": round(bms, 4),
+                      "eager_sequence_ms": round(ems, 4), "ns_per_triangle": round(bms * 1e6 / ntri, 3),
+                      "alg_bytes": abytes, "gbps": round(abytes / bms / 1e6, 1),
+                      "largest_mesh_alone": {"triangles": inf["rows"], "ms": round(sms, 4),
+                                             "ns_per_triangle": round(sms * 1e6 / inf["rows"], 3),
+                                             "gbps": round(alg_bytes(inf, 4)["total"] / sms / 1e6, 1)}}
+    log("batch of 16 meshes (%d triangles): one graph launch %.3f ms (%.2f ns per triangle, %.0f GB/s), "
+        "eager sequence %.3f ms; largest mesh alone %.3f ms (%.2f ns per triangle)"
+        % (ntri, bms, bms * 1e6 / ntri, abytes / bms / 1e6, ems, sms, sms * 1e6 / inf["rows"]))
+    # the same meshes with 64 right-hand sides each
+    items64 = []
+    for k, (op, _, _) in enumerate(items):
+        X = torch.tensor(synth.random_vector(op.shape[1], 630 + k, cols=64), device=dev).t().contiguous().t()
+        Y = torch.zeros((64, op.shape[0]), dtype=torch.float64, device=dev).t()
+        items64.append((op, X, Y))
+    batch64 = h2b.Batch(items64)
+    b64 = timed(batch64.launch, 2 * reps)
+    e64 = timed(lambda: [op.matvec(X, Y) for op, X, Y in items64], reps)
+    res["batch16_64rhs"] = {"meshes": 16, "triangles": ntri, "rhs": 64, "graph_launch_ms": round(b64, 4),
+                            "eager_sequence_ms": round(e64, 4),
+                            "ns_per_triangle_rhs": round(b64 * 1e6 / ntri / 64, 4)}
+    log("batch of 16 meshes x 64 right-hand sides: one graph launch %.3f ms (%.3f ns per triangle and "
+        "right-hand side), eager sequence %.3f ms" % (b64, b64 * 1e6 / ntri / 64, e64))
+    del batch, batch64
     return res
 
 

@@ -64,6 +64,32 @@ typedef struct h2b_blocks_s *h2b_blocks;
 typedef struct h2b_op_s *h2b_op;
 typedef struct h2b_batch_s *h2b_batch;
 
+/* ------------------------------------------------------ device memory */
+
+/* Device allocator callbacks.  alloc returns `bytes` of device memory on the
+ * current HIP device (aligned to at least 256 bytes), or NULL if it cannot;
+ * hip_stream is the stream of the library call that asks (NULL for the
+ * default stream), ctx the pointer given to h2b_set_allocator.  free returns
+ * a block obtained from alloc, with the same stream and ctx. */
+typedef void *(*h2b_alloc_fn)(size_t bytes, void *hip_stream, void *ctx);
+typedef void (*h2b_free_fn)(void *ptr, void *hip_stream, void *ctx);
+
+/* Installs the allocator of all device memory the library takes from now on:
+ * operator storage (nearfield, bases, couplings, transposed copies,
+ * descriptors), product work vectors, batch and solver work vectors.  With
+ * alloc = free = NULL the library uses hipMalloc and hipFree again (the
+ * default).  The setting is process-wide.  Every block remembers the
+ * allocator it came from and is returned to it (so blocks taken before a
+ * change are still freed correctly); before it returns a block the library
+ * waits for the device (as hipFree does), so the allocator may hand the block
+ * out again at once.  A NULL result of alloc makes the call that needed the
+ * memory fail with H2B_ENOMEM, with no handle created and no output written;
+ * a block that is not 256-byte aligned is returned and the call fails with
+ * H2B_EINVAL.  The Python binding installs torch's caching allocator at
+ * import, so the operators' memory shows in torch.cuda.memory_allocated().
+ * Errors: H2B_EINVAL if exactly one of alloc and free is NULL. */
+h2b_status h2b_set_allocator(h2b_alloc_fn alloc, h2b_free_fn free, void *ctx);
+
 /* Thread-local text of the last error ("" if none). */
 const char *h2b_last_error(void);
 
@@ -173,10 +199,18 @@ typedef struct {
                                the normal derivative in y of Green's formula (Section 5).  G must
                                be on one tree (H2B_ENOTSUP otherwise); excludes recompress_tol
                                (H2B_EINVAL); 0 (default): interpolation */
+    int recompute_coupling; /* 1: store no coupling matrices; every product evaluates
+                               S_ts = g(xi_t, xi_s) at the interpolation points again (Section 2,
+                               eq. (vsw); Section 3), trading their storage (the largest stored
+                               object: k^2 values per farfield block) for k_t k_s kernel evaluations
+                               per block.  With recompression the projections of the recompressed
+                               bases onto the interpolation bases are stored instead (k'_t k values
+                               per cluster) and applied once per cluster.  FP64 far field only and
+                               not with gca_tol (H2B_ENOTSUP); 0 (default): stored couplings */
 } h2b_params;
 
 /* Fills p with the defaults: order_m 4, q_near 4, recompress_tol 0, F64,
- * transposed_copy 1, symmetric_near 1, gca_tol 0. */
+ * transposed_copy 1, symmetric_near 1, gca_tol 0, recompute_coupling 0. */
 void h2b_params_default(h2b_params *p);
 
 /* Assembles G (kernel H2B_SLP, cols tree P0) or K (H2B_DLP, cols tree P1) on
@@ -210,6 +244,7 @@ typedef struct {
     int64_t near_sym_entries;      /* entries of the once-per-pair nearfield (0 if none) */
     int64_t near_sym_columns;      /* its panel columns (one column sum each per product) */
     int64_t near_sym_corrections;  /* touching pairs across leaves (corrections per product) */
+    int64_t coupling_evals;        /* kernel evaluations per product (recompute_coupling; else 0) */
 } h2b_op_stats;
 
 h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
@@ -293,6 +328,20 @@ h2b_status h2b_op_set_geometry(h2b_op op, const double *vx, const double *vy, co
                                void *hip_stream);
 h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double *gvx, double *gvy,
                               double *gvz, void *hip_stream);
+
+/* The discrete single-layer bilinear form b = x^T G y (Section 1, eq. (slp),
+ * with the H^2 approximation of G): gy = G y (overwritten) and
+ * out[0] = x^T gy, an FP64 inner product reduced in a fixed order (the same
+ * bits for the same input on the same device).  x, y, gy: device arrays of nt
+ * doubles (triangle order); out: one device double.  This is the forward
+ * value of the shape-differentiable form whose derivative
+ * h2b_slp_shape_grad gives; gy is kept for the derivative in x.  Uses the
+ * operator's work vectors (no overlap with other calls on G).  Runs
+ * asynchronously on hip_stream.
+ * Errors: H2B_EINVAL if G is not the single-layer operator, for a NULL
+ * pointer, gy overlapping x or y, or out overlapping x or gy. */
+h2b_status h2b_slp_bilinear(h2b_op G, const double *x, const double *y, double *gy, double *out,
+                            void *hip_stream);
 
 /* Per-phase timing of the products on an operator, measured with HIP events on
  * the streams the phases run on.  A product runs its nearfield on a stream of

@@ -29,6 +29,11 @@ systems and the conjugate gradient method, dense and in double precision
   W u = (M^T/2 - K^T) t.  W annihilates constants, so the discrete Dirichlet
   data are fixed up to a constant; the direct solve here picks the solution
   with int u_h = 0 (an added Lagrange multiplier).
+* Discrete H^{-1/2} error of the Neumann data (Section 5, the energy-norm
+  error the experiments report beside the L2 error): for the P0 L2
+  projection Pi t of the exact normal derivative and the computed t_h, the
+  single-layer operator defines the norm, ||e||_G = sqrt(e^T G e) with
+  e = Pi t - t_h.  A plain matrix form; G is symmetric positive definite.
 * The test functions of Section 5: u1(x) = x1^2 - x3^2, u2 = g(., y1) and
   u3 = g(., y2) with y1 = (1.2, 1.2, 1.2), y2 = (1.0, 0.25, 1.0), all
   harmonic inside the unit sphere, and the L2 error of a piecewise constant
@@ -292,3 +297,17 @@ def neumann_projection(verts, tris, grad_u, q=6):
     X = a[:, None, :] + U[None, :, :1] * (b - a)[:, None, :] + U[None, :, 1:2] * (c - b)[:, None, :]
     dn = np.einsum("ikd,id->ik", grad_u(X), n)
     return (dn * W[None, :]).sum(axis=1) / W.sum()
+
+
+def energy_norm(G, e):
+    """sqrt(e^T G e), the norm that the single-layer matrix G defines on
+    piecewise constant coefficient vectors (an approximation of the
+    H^{-1/2} norm of the function)."""
+    e = np.asarray(e, dtype=np.float64)
+    return math.sqrt(float(e @ (G @ e)))
+
+
+def neumann_energy_error(G, verts, tris, t, grad_u, q=6):
+    """||Pi t - t_h||_G: the discrete H^{-1/2} error of the Neumann
+    coefficients t against the P0 projection of <grad u, n_tau>."""
+    return energy_norm(G, neumann_projection(verts, tris, grad_u, q) - np.asarray(t, dtype=np.float64))

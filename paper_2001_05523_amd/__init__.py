@@ -40,7 +40,8 @@ _P = ctypes.POINTER
 class h2b_params(ctypes.Structure):
     _fields_ = [("order_m", ctypes.c_int), ("q_near", ctypes.c_int),
                 ("recompress_tol", ctypes.c_double), ("farfield_dtype", ctypes.c_int),
-                ("transposed_copy", ctypes.c_int), ("symmetric_near", ctypes.c_int), ("gca_tol", ctypes.c_double)]
+                ("transposed_copy", ctypes.c_int), ("symmetric_near", ctypes.c_int), ("gca_tol", ctypes.c_double),
+                ("recompute_coupling", ctypes.c_int)]
 
 
 class h2b_op_stats(ctypes.Structure):
@@ -51,7 +52,8 @@ class h2b_op_stats(ctypes.Structure):
                 ("row_coeffs", _i64), ("col_coeffs", _i64),
                 ("max_rank_row", _i32), ("max_rank_col", _i32),
                 ("mean_rank_row", _dbl), ("mean_rank_col", _dbl), ("bytes_transposed", _i64),
-                ("near_sym_entries", _i64), ("near_sym_columns", _i64), ("near_sym_corrections", _i64)]
+                ("near_sym_entries", _i64), ("near_sym_columns", _i64), ("near_sym_corrections", _i64),
+                ("coupling_evals", _i64)]
 
 
 class h2b_cg_params(ctypes.Structure):
@@ -98,6 +100,7 @@ _SIGS = {
     "h2b_batch_destroy": ([_vp], ctypes.c_int),
     "h2b_op_set_geometry": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "h2b_slp_shape_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_slp_bilinear": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "h2b_op_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_set_overlap": ([_vp, ctypes.c_int], ctypes.c_int),
     "h2b_op_phase_times": ([_vp, _vp], ctypes.c_int),
@@ -107,6 +110,10 @@ _SIGS = {
     "h2b_hypersingular_matvec": ([_vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
 }
 
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+_SIGS["h2b_set_allocator"] = ([_ALLOC_FN, _FREE_FN, _vp], ctypes.c_int)
+
 EXPORTED = tuple(_SIGS)
 
 for _name, (_args, _res) in _SIGS.items():
@@ -114,6 +121,52 @@ for _name, (_args, _res) in _SIGS.items():
     _f.argtypes = _args
     _f.restype = _res
     globals()[_name] = _f
+
+
+# ------------------------------------------------------- device memory
+#
+# The library's device memory (operators, work vectors) comes from torch's
+# caching allocator: it shows in torch.cuda.memory_allocated() and shares
+# torch's pool.  The callbacks run with the GIL (ctypes takes it).
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except RuntimeError:  # out of memory: the library reports H2B_ENOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+
+
+def use_torch_allocator():
+    """Device memory of the library from torch's caching allocator (the
+    default after import)."""
+    _check(h2b_set_allocator(_TORCH_ALLOC, _TORCH_FREE, None))
+
+
+def use_hip_allocator():
+    """Device memory of the library from hipMalloc / hipFree."""
+    _check(h2b_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+
+
+# Handles still alive when the interpreter exits are not destroyed: their
+# memory would go back to torch's allocator while torch itself is shutting
+# down.  The process ends and the driver frees everything anyway.
+_EXITING = [False]
+
+
+def _at_exit():
+    _EXITING[0] = True
+
+
+import atexit  # noqa: E402
+atexit.register(_at_exit)
 
 
 class H2BError(RuntimeError):
@@ -129,6 +182,9 @@ def _check(code):
 
 def _ptr(a):
     return a.ctypes.data_as(_vp)
+
+
+use_torch_allocator()
 
 
 # --------------------------------------------------------------- handles
@@ -148,7 +204,7 @@ class Mesh:
         self.nv, self.nt = len(v), len(t)
 
     def __del__(self, _destroy=h2b_mesh_destroy):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and not _EXITING[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -183,7 +239,7 @@ class Tree:
         return ranks, [piv[offs[c]:offs[c + 1]] for c in range(self.nclusters)]
 
     def __del__(self, _destroy=h2b_tree_destroy):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and not _EXITING[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -205,7 +261,7 @@ class Blocks:
         return far, near
 
     def __del__(self, _destroy=h2b_blocks_destroy):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and not _EXITING[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -234,7 +290,8 @@ class Operator:
 
     def __init__(self, verts=None, tris=None, kernel="slp", leaf=32, order_m=4, q_near=4,
                  eta=1.0, far_disabled=False, recompress_tol=0.0, farfield_dtype="f64",
-                 transposed_copy=True, symmetric_near=True, gca_tol=0.0, stream=None, mesh=None):
+                 transposed_copy=True, symmetric_near=True, gca_tol=0.0, recompute_coupling=False, stream=None,
+                 mesh=None):
         self.mesh = mesh if mesh is not None else Mesh(verts, tris)
         self.kernel = H2B_SLP if kernel == "slp" else H2B_DLP
         self.rows = Tree(self.mesh, H2B_P0, leaf)
@@ -242,7 +299,8 @@ class Operator:
         self.blocks = Blocks(self.rows, self.cols, eta, far_disabled)
         p = default_params(order_m=order_m, q_near=q_near, recompress_tol=recompress_tol,
                            farfield_dtype=_DTYPES[farfield_dtype], transposed_copy=int(bool(transposed_copy)),
-                           symmetric_near=int(bool(symmetric_near)), gca_tol=float(gca_tol))
+                           symmetric_near=int(bool(symmetric_near)), gca_tol=float(gca_tol),
+                           recompute_coupling=int(bool(recompute_coupling)))
         h = _vp()
         _check(h2b_assemble(self.blocks.handle, self.kernel, ctypes.byref(p), _stream_ptr(stream),
                             ctypes.byref(h)))
@@ -366,7 +424,7 @@ class Operator:
         return out
 
     def __del__(self, _destroy=h2b_op_destroy):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and not _EXITING[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -431,7 +489,7 @@ class Batch:
         _check(h2b_batch_launch(self.handle, _stream_ptr(stream)))
 
     def __del__(self, _destroy=h2b_batch_destroy):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and not _EXITING[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -439,21 +497,27 @@ class Batch:
 class SlpBilinear(torch.autograd.Function):
     """b = x^T G(verts) y for the H^2 single-layer matrix of an Operator built
     with recompress_tol = 0; the cluster trees, boxes and interpolation points
-    stay frozen at the operator's construction geometry.  The backward pass
-    uses the library's adjoint kernels for d b / d verts and the products
-    G y and G^T x for the vectors.
+    stay frozen at the operator's construction geometry.  The forward value
+    comes from h2b_slp_bilinear (G y and the inner product in the library);
+    the backward pass uses the library's adjoint kernels for d b / d verts and
+    G y, G^T x for the vectors, scaled by the incoming gradient (autograd's
+    chain rule).
 
         b = SlpBilinear.apply(verts, x, y, op)"""
 
     @staticmethod
     def forward(ctx, verts, x, y, op):
         op.set_geometry(verts.detach().cpu().numpy())
-        gy = torch.zeros_like(x)
-        op.matvec(y, gy)
+        gy = torch.empty_like(x)
+        b = torch.empty((), dtype=torch.float64, device=x.device)
+        _vector(x, op.mesh.nt, "x")
+        _vector(y, op.mesh.nt, "y")
+        _check(h2b_slp_bilinear(op.handle, _vp(x.data_ptr()), _vp(y.data_ptr()), _vp(gy.data_ptr()),
+                                _vp(b.data_ptr()), _stream_ptr(None)))
         ctx.save_for_backward(x, y, gy)
         ctx.op = op
         ctx.vspec = (verts.device, verts.dtype)
-        return torch.dot(x, gy)
+        return b
 
     @staticmethod
     def backward(ctx, gout):

@@ -1,5 +1,7 @@
 // Batched products over several operators (meshes of different sizes)
-// captured once into a hipGraph on one stream: each operator's product starts
+// captured once into a hipGraph.  Products that share one program (same
+// far-field type, direction and number of right-hand sides) are merged step by
+// step (batch_merged.hip).  Otherwise each operator's product starts
 // a new root of the graph (the stream's capture dependencies are cleared
 // before it), so the products of different meshes are independent branches.
 // Inside the batch each product keeps its phases in sequence: splitting every
@@ -38,16 +40,36 @@ std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, 
             fail(H2B_EINVAL, "an operator appears twice (its work vectors would be shared)");
         // argument checks and block buffers happen before the capture
         check_product_args(*ops[i], trans[i], x[i], ldx[i], y[i], ldy[i], nrhs[i]);
-        prepare_product(*ops[i], nrhs[i]);
     }
     // the caller's stream may be the null stream, which cannot be captured:
     // capture on a private stream and launch the graph on the caller's
     // stream later
-    (void)st;
     auto b = std::make_unique<Batch>();
     b->streams.resize(1, nullptr);
     hip_check(hipStreamCreateWithFlags(&b->streams[0], hipStreamNonBlocking), "stream create");
     hipStream_t cap = b->streams[0];
+    // products that share one program run merged: one launch per step for the
+    // whole batch, with work vectors of the batch's own
+    b->merged = merged_create(nops, ops, trans, alpha, x, ldx, y, ldy, nrhs, st);
+    if (b->merged) {
+        hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+            merged_capture(*b->merged, cap);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(cap, &b->graph), "end capture");
+        hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+        return b;
+    }
+    // the graph keeps the addresses of the operators' work vectors: block
+    // vectors are reserved at the widest block so that nothing reallocates
+    // them while the batch exists (a later h2b_op_tune or wider product)
+    for (int i = 0; i < nops; ++i)
+        if (nrhs[i] > 1) reserve_block_buffers(*ops[i]);
     // the products stay sequential inside the capture (overlap off), restored
     // on every exit
     struct OverlapOff {

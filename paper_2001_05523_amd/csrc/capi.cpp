@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "op.hpp"
@@ -23,6 +24,33 @@ struct h2b_op_s {
 struct h2b_batch_s {
     std::unique_ptr<h2b::Batch> b;
 };
+
+namespace h2b {
+
+namespace {
+std::mutex g_alloc_mu;
+DeviceAllocator g_alloc;
+thread_local hipStream_t g_alloc_stream = nullptr;
+}  // namespace
+
+DeviceAllocator current_allocator()
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+void set_allocator(const DeviceAllocator &a)
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = a;
+}
+
+hipStream_t alloc_stream() { return g_alloc_stream; }
+
+AllocStreamScope::AllocStreamScope(hipStream_t st) : saved(g_alloc_stream) { g_alloc_stream = st; }
+AllocStreamScope::~AllocStreamScope() { g_alloc_stream = saved; }
+
+}  // namespace h2b
 
 namespace {
 
@@ -59,6 +87,19 @@ void need(const void *p, const char *what)
 extern "C" {
 
 const char *h2b_last_error(void) { return g_err.c_str(); }
+
+h2b_status h2b_set_allocator(h2b_alloc_fn alloc, h2b_free_fn free, void *ctx)
+{
+    return guarded([&] {
+        if ((alloc == nullptr) != (free == nullptr))
+            h2b::fail(H2B_EINVAL, "alloc and free must both be set or both be NULL");
+        h2b::DeviceAllocator a;
+        a.alloc = alloc;
+        a.free = free;
+        a.ctx = alloc ? ctx : nullptr;
+        h2b::set_allocator(a);
+    });
+}
 
 const char *h2b_version(void) { return "h2bem 0.1 (gfx950)"; }
 
@@ -203,12 +244,14 @@ void h2b_params_default(h2b_params *p)
     p->transposed_copy = 1;
     p->symmetric_near = 1;
     p->gca_tol = 0.0;
+    p->recompute_coupling = 0;
 }
 
 h2b_status h2b_assemble(h2b_blocks blocks, h2b_kernel kernel, const h2b_params *params,
                         void *hip_stream, h2b_op *out)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(blocks, "blocks");
         need(params, "params");
         need(out, "out");
@@ -236,6 +279,7 @@ h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64
                       int64_t ldy, int nrhs, void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(op, "op");
         h2b::matvec(*op->op, trans ? 1 : 0, alpha, x, ldx, y, ldy, nrhs,
                     static_cast<hipStream_t>(hip_stream));
@@ -247,6 +291,7 @@ h2b_status h2b_batch_create(int nops, const h2b_op *ops, const int *trans, const
                             const int64_t *ldy, const int *nrhs, void *hip_stream, h2b_batch *out)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(ops, "ops");
         need(out, "out");
         std::vector<h2b::Op *> raw(nops > 0 ? nops : 0);
@@ -277,6 +322,7 @@ h2b_status h2b_batch_destroy(h2b_batch batch)
 h2b_status h2b_op_tune(h2b_op op, int nrhs, void *hip_stream, double *best_us)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(op, "op");
         h2b::tune(*op->op, nrhs, static_cast<hipStream_t>(hip_stream), best_us);
     });
@@ -286,6 +332,7 @@ h2b_status h2b_op_set_geometry(h2b_op op, const double *vx, const double *vy, co
                                void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(op, "op");
         h2b::set_geometry(*op->op, vx, vy, vz, static_cast<hipStream_t>(hip_stream));
     });
@@ -295,8 +342,19 @@ h2b_status h2b_slp_shape_grad(h2b_op G, const double *x, const double *y, double
                               double *gvz, void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(G, "G");
         h2b::slp_shape_grad(*G->op, x, y, gvx, gvy, gvz, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h2b_status h2b_slp_bilinear(h2b_op G, const double *x, const double *y, double *gy, double *out,
+                            void *hip_stream)
+{
+    return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
+        need(G, "G");
+        h2b::slp_bilinear(*G->op, x, y, gy, out, static_cast<hipStream_t>(hip_stream));
     });
 }
 
@@ -341,6 +399,7 @@ void h2b_cg_params_default(h2b_cg_params *p)
 h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, double *y, void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(G, "G");
         h2b::hypersingular_matvec(*G->op, alpha, x, y, static_cast<hipStream_t>(hip_stream));
     });
@@ -349,6 +408,7 @@ h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, dou
 h2b_status h2b_mass_matvec(h2b_op op, int trans, double alpha, const double *x, double *y, void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(op, "op");
         h2b::mass_matvec(*op->op, trans ? 1 : 0, alpha, x, y, static_cast<hipStream_t>(hip_stream));
     });
@@ -358,6 +418,7 @@ h2b_status h2b_cg_solve(h2b_op A, const double *b, double *x, const h2b_cg_param
                         h2b_cg_result *result, double *history, void *hip_stream)
 {
     return guarded([&] {
+        h2b::AllocStreamScope scope(static_cast<hipStream_t>(hip_stream));
         need(A, "A");
         need(params, "params");
         need(result, "result");

@@ -132,6 +132,14 @@ __global__ __launch_bounds__(KT) void k_sub_shift(const double *a, const double 
         y[i] = a[i] - c * (w ? w[i] : 1.0);
 }
 
+// *out = sum of part[0..nb) (the second stage of a dot product).
+__global__ __launch_bounds__(KT) void k_parts_to(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    __shared__ double lds[KT / 64];
+    const double s = parts_total(part, nb, lds);
+    if (threadIdx.x == 0) *out = s;
+}
+
 // alpha = rho / p^T q (0 once stopped; breakdown when p^T q is not positive).
 __global__ __launch_bounds__(KT) void k_cg_alpha(const double *__restrict__ part, int nb, CgState *S)
 {
@@ -487,6 +495,26 @@ void hypersingular_matvec(Op &G, double alpha, const double *x, double *y, hipSt
     hipLaunchKernelGGL(k_curl_corners, dim3(grid_for(nt)), dim3(KT), 0, st, G.geo, nt, gc, c);
     hipLaunchKernelGGL(k_curl_t, dim3(grid_for(nv)), dim3(KT), 0, st, G.geo, nv, c, alpha, y);
     hip_check(hipGetLastError(), "curl transpose launch");
+}
+
+void slp_bilinear(Op &G, const double *x, const double *y, double *gy, double *out, hipStream_t st)
+{
+    if (G.kernel != H2B_SLP) fail(H2B_EINVAL, "the bilinear form needs the single-layer operator G");
+    if (!x || !y || !gy || !out) fail(H2B_EINVAL, "NULL vector");
+    const int64_t n = G.nrows;
+    if (overlaps(gy, sizeof(double) * n, x, sizeof(double) * n) || overlaps(out, sizeof(double), gy, sizeof(double) * n) ||
+        overlaps(out, sizeof(double), x, sizeof(double) * n))
+        fail(H2B_EINVAL, "gy must not overlap x, and out none of x and gy");
+    check_product_args(G, 0, y, n, gy, n, 1);
+    launch_fill_zero<double>(gy, n, st);
+    matvec(G, 0, 1.0, y, n, gy, n, 1, st);
+    // the product has ended on st (its nearfield branch is joined before its
+    // last kernel), so its permuted-input vector holds the partial sums
+    const int nb = grid_for(n);
+    double *part = G.xp.as<double>();
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(KT), 0, st, x, gy, n, part);
+    hipLaunchKernelGGL(k_parts_to, dim3(1), dim3(KT), 0, st, part, nb, out);
+    hip_check(hipGetLastError(), "bilinear form launch");
 }
 
 void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_cg_result &res, double *history,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -223,13 +224,22 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (!(p.gca_tol >= 0.0) || !std::isfinite(p.gca_tol)) fail(H2B_EINVAL, "gca_tol must be finite and >= 0");
     const bool gca = p.gca_tol > 0.0;
     if (gca && p.recompress_tol > 0.0) fail(H2B_EINVAL, "choose either recompression or the Green cross approximation");
-    if (gca && kernel == H2B_SLP && blocks->rows != blocks->cols)
-        fail(H2B_ENOTSUP, "the Green cross approximation of G needs one cluster tree");
+    if (kernel == H2B_SLP && blocks->rows != blocks->cols)
+        fail(H2B_EINVAL, "the single-layer matrix needs one cluster tree for its rows and columns");
+    // Reduced-precision storage keeps the error of the far field at the level
+    // of the FP32/BF16 rounding only for orthonormal cluster bases, i.e. after
+    // the algebraic recompression; interpolation and cross-approximation bases
+    // are not orthonormal and amplify it.
+    if (p.farfield_dtype != H2B_F64 && !(p.recompress_tol > 0.0))
+        fail(H2B_ENOTSUP, "an FP32 or BF16 far field needs orthonormal bases (recompress_tol > 0)");
+    if (p.recompute_coupling && (p.farfield_dtype != H2B_F64 || gca))
+        fail(H2B_ENOTSUP, "evaluated couplings need an FP64 interpolation far field (no gca_tol)");
 
     auto op = std::make_unique<Op>();
     op->blocks = blocks;
     op->kernel = kernel;
     op->params = p;
+    op->recompute = p.recompute_coupling != 0;
     const Tree &R = *blocks->rows, &C = *blocks->cols;
     const Mesh &M = *R.mesh;
     op->nrows = R.n;
@@ -333,7 +343,9 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (gca) {
         set_gca_values(*op, gb, op->colb != op->rowb ? gbc : gb, st);
     } else {
-    op->cpl_vals.alloc(coupling_size(adt) * std::max<int64_t>(op->cpl.total, 1));
+    // evaluated couplings are not stored, except transiently for the recompression
+    const bool store_cpl = !op->recompute || rc;
+    if (store_cpl) op->cpl_vals.alloc(coupling_size(adt) * std::max<int64_t>(op->cpl.total, 1));
     for (Basis *B : bases) {
         if (adt == H2B_F64)
             assemble_basis<double>(*B, m, B->axes, op->geo, st);
@@ -342,7 +354,9 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
         transpose_basis_values(*B, adt, st);
     }
     const double *rax = op->rowb->axes.as<double>(), *cax = op->colb->axes.as<double>();
-    if (adt == H2B_F64)
+    if (!store_cpl)
+        ;
+    else if (adt == H2B_F64)
         launch_coupling<double>(op->cpl, rax, cax, m, op->cpl_vals.as<double>(), st);
     else if (adt == H2B_F32)
         launch_coupling<float>(op->cpl, rax, cax, m, op->cpl_vals.as<float>(), st);
@@ -352,6 +366,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     hip_check(hipStreamSynchronize(st), "assembly");
     if (rc) recompress_op(*op, p.recompress_tol, st);
     if (p.transposed_copy) make_transposed_copies(*op, st);
+    if (op->recompute) setup_recompute(*op, st);
     // the once-per-pair kernel keeps a leaf's rows in LDS: leaves of at most 64
     if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols && op->near.max_nrows <= 64 &&
         op->near.ngroups() > 0)
@@ -369,6 +384,11 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     hip_check(hipEventCreateWithFlags(&op->join, hipEventDisableTiming), "event create");
     op->xhat.alloc(wsz * std::max<int64_t>(hmax, 1));
     op->yhat.alloc(wsz * std::max<int64_t>(hmax, 1));
+    if (op->rowb->has_proj) {
+        const int64_t kc = (int64_t)k * std::max(R.nclusters(), C.nclusters());
+        op->xt.alloc(sizeof(double) * kc);
+        op->yt.alloc(sizeof(double) * kc);
+    }
     return op;
 }
 
@@ -381,11 +401,13 @@ void make_transposed_copies(Op &op, hipStream_t st)
         op.near_R.upload(st);
         op.cpl_R.upload(st);
         op.near_R_vals.alloc(sizeof(double) * std::max<int64_t>(op.near_R.total, 1));
-        op.cpl_R_vals.alloc(coupling_size(dt) * std::max<int64_t>(op.cpl_R.total, 1));
+        if (!op.recompute) op.cpl_R_vals.alloc(coupling_size(dt) * std::max<int64_t>(op.cpl_R.total, 1));
     }
     launch_regroup_transpose<double>(op.near_T, op.near_R, op.near_vals.as<double>(), op.near_R_vals.as<double>(),
                                      st);
-    if (dt == H2B_F64)
+    if (op.recompute)
+        ;  // no stored couplings: cpl_R only groups the blocks by column cluster
+    else if (dt == H2B_F64)
         launch_regroup_transpose<double>(op.cpl_T, op.cpl_R, op.cpl_vals.as<double>(),
                                          op.cpl_R_vals.as<double>(), st);
     else if (dt == H2B_F32)
@@ -463,6 +485,17 @@ static void join_side(Op &op, hipStream_t ns, hipStream_t st)
     hip_check(hipStreamWaitEvent(st, op.join, 0), "stream wait");
 }
 
+// Work vectors of one product (rb = 1 for a single vector, else the block
+// width): the operator's own, or views into the static scratch array of the
+// allocation-free entry point.  `sym` allows the once-per-pair nearfield of G
+// (whose column sums live in the operator); `timed` allows phase events.
+struct Work {
+    double *xp, *yp, *ypn;
+    void *xhat, *yhat;
+    bool sym, timed;
+    double *xt, *yt;  // interpolation coefficients of evaluated couplings on recompressed bases
+};
+
 // The four pieces of one product.  Prepare clears the outputs and gathers x
 // into cluster order; Near (nearfield into ypn) and Far (forward
 // transformation, coupling, backward transformation into yp) both read only
@@ -472,15 +505,15 @@ static void join_side(Op &op, hipStream_t ns, hipStream_t st)
 enum class Piece { Prepare, Near, Far, Finish };
 
 template <typename F, typename C>
-static void product_piece(Op &op, int trans, double alpha, const double *x, double *y, Piece pc, hipStream_t st,
-                          hipEvent_t *ev)
+static void product_piece(Op &op, const Work &w, int trans, double alpha, const double *x, double *y, Piece pc,
+                          hipStream_t st, hipEvent_t *ev)
 {
     const Basis &Bin = trans ? *op.rowb : *op.colb;
     const Basis &Bout = trans ? *op.colb : *op.rowb;
     const int64_t nin = trans ? op.nrows : op.ncols;
     const int64_t nout = trans ? op.ncols : op.nrows;
-    double *xp = op.xp.as<double>(), *yp = op.yp.as<double>(), *ypn = op.ypn.as<double>();
-    F *xhat = op.xhat.as<F>(), *yhat = op.yhat.as<F>();
+    double *xp = w.xp, *yp = w.yp, *ypn = w.ypn;
+    F *xhat = static_cast<F *>(w.xhat), *yhat = static_cast<F *>(w.yhat);
     auto mark = [&](int i) {
         if (ev) hip_check(hipEventRecord(ev[i], st), "event record");
     };
@@ -495,7 +528,7 @@ static void product_piece(Op &op, int trans, double alpha, const double *x, doub
     case Piece::Near:
         launch_fill_zero<double>(ypn, nout, st);
         mark(5);
-        if (op.sym)
+        if (op.sym && w.sym)
             symmetric_near_product(op, trans, xp, ypn, st);
         else if (!trans)
             launch_rowpanel<double, double, double>(op.near, 0, op.near.ngroups(), op.near_vals.as<double>(), xp,
@@ -511,6 +544,15 @@ static void product_piece(Op &op, int trans, double alpha, const double *x, doub
     case Piece::Far:
         forward<F>(Bin, xp, xhat, st);
         mark(2);
+        if constexpr (std::is_same<F, double>::value) {
+            if (op.recompute) {
+                recompute_coupling(op, trans, 1, xhat, yhat, w.xt, w.yt, st);
+                mark(3);
+                backward<F>(Bout, yhat, yp, st);
+                mark(4);
+                break;
+            }
+        }
         if (!trans)
             launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, yhat, true, st,
                                      Role::Coupling);
@@ -548,7 +590,7 @@ void set_capture_tail(hipStream_t st, std::vector<hipGraphNode_t> deps)
 }
 
 template <typename F, typename C>
-static void product_one(Op &op, int trans, double alpha, const double *x, double *y, hipStream_t st)
+static void product_one(Op &op, const Work &w, int trans, double alpha, const double *x, double *y, hipStream_t st)
 {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hip_check(hipStreamIsCapturing(st, &cs), "capture status");
@@ -556,28 +598,28 @@ static void product_one(Op &op, int trans, double alpha, const double *x, double
         // captured into a graph: the nearfield and the far field become two
         // parallel branches after the gather, made on this one stream by
         // resetting what the next captured work depends on
-        product_piece<F, C>(op, trans, alpha, x, y, Piece::Prepare, st, nullptr);
+        product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Prepare, st, nullptr);
         const std::vector<hipGraphNode_t> prep = capture_tail(st);
-        product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, st, nullptr);
+        product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Near, st, nullptr);
         std::vector<hipGraphNode_t> ends = capture_tail(st);
         set_capture_tail(st, prep);
-        product_piece<F, C>(op, trans, alpha, x, y, Piece::Far, st, nullptr);
+        product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Far, st, nullptr);
         const std::vector<hipGraphNode_t> far = capture_tail(st);
         ends.insert(ends.end(), far.begin(), far.end());
         set_capture_tail(st, ends);
-        product_piece<F, C>(op, trans, alpha, x, y, Piece::Finish, st, nullptr);
+        product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Finish, st, nullptr);
         return;
     }
-    hipEvent_t *ev = event_set(op, st);
-    product_piece<F, C>(op, trans, alpha, x, y, Piece::Prepare, st, ev);
+    hipEvent_t *ev = w.timed ? event_set(op, st) : nullptr;
+    product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Prepare, st, ev);
     // nearfield on the side stream from here, or on st after the far field
     hipStream_t ns = fork_side(op, st);
-    if (ns != st) product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, ns, ev);
-    product_piece<F, C>(op, trans, alpha, x, y, Piece::Far, st, ev);
-    if (ns == st) product_piece<F, C>(op, trans, alpha, x, y, Piece::Near, st, ev);
+    if (ns != st) product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Near, ns, ev);
+    product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Far, st, ev);
+    if (ns == st) product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Near, st, ev);
     join_side(op, ns, st);
     if (ev) hip_check(hipEventRecord(ev[7], st), "event record");
-    product_piece<F, C>(op, trans, alpha, x, y, Piece::Finish, st, ev);
+    product_piece<F, C>(op, w, trans, alpha, x, y, Piece::Finish, st, ev);
 }
 
 // ------------------------------------------------ many right-hand sides
@@ -602,12 +644,26 @@ static void ensure_block_buffers(Op &op, int rb)
     op.xhatb.alloc(fsz * hmax * rb);
     op.yhatb.alloc(fsz * hmax * rb);
     op.ypbn.alloc(sizeof(double) * nmax * rb);
+    if (op.rowb->has_proj) {
+        const int k = op.params.order_m * op.params.order_m * op.params.order_m;
+        const int64_t kc = (int64_t)k * std::max(op.rowb->tree->nclusters(), op.colb->tree->nclusters());
+        op.xtb.alloc(sizeof(double) * kc * rb);
+        op.ytb.alloc(sizeof(double) * kc * rb);
+    }
     op.mrhs_rb = rb;
 }
 
 template <typename F, typename C>
-static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *yhat, hipStream_t st)
+static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *yhat, hipStream_t st,
+                           double *xt = nullptr, double *yt = nullptr)
 {
+    if constexpr (std::is_same<F, double>::value) {
+        if (op.recompute) {
+            recompute_coupling(op, trans, rb, xhat, yhat, xt ? xt : op.xtb.as<double>(), yt ? yt : op.ytb.as<double>(),
+                               st);
+            return;
+        }
+    }
     if (trans && !op.has_R) {
         launch_colpanel_mrhs<C, F, F>(op.cpl_T, 0, op.cpl_T.ngroups(), rb, op.cpl_vals.as<C>(), xhat, yhat, true,
                                       st, Role::Coupling);
@@ -630,16 +686,16 @@ static void coupling_block(Op &op, int trans, int rb, int kc, const F *xhat, F *
 
 // Product for nb <= rb right-hand sides at once (block vectors row-major).
 template <typename F, typename C>
-static void product_block(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y,
+static void product_block(Op &op, const Work &w, int trans, double alpha, const double *x, int64_t ldx, double *y,
                           int64_t ldy, int nb, int rb, hipStream_t st)
 {
     const Basis &Bin = trans ? *op.rowb : *op.colb;
     const Basis &Bout = trans ? *op.colb : *op.rowb;
     const int64_t nin = trans ? op.nrows : op.ncols;
     const int64_t nout = trans ? op.ncols : op.nrows;
-    double *xp = op.xpb.as<double>(), *yp = op.ypb.as<double>(), *ypn = op.ypbn.as<double>();
-    F *xhat = op.xhatb.as<F>(), *yhat = op.yhatb.as<F>();
-    hipEvent_t *ev = event_set(op, st);
+    double *xp = w.xp, *yp = w.yp, *ypn = w.ypn;
+    F *xhat = static_cast<F *>(w.xhat), *yhat = static_cast<F *>(w.yhat);
+    hipEvent_t *ev = w.timed ? event_set(op, st) : nullptr;
     auto mark = [&](int i, hipStream_t s) {
         if (ev) hip_check(hipEventRecord(ev[i], s), "event record");
     };
@@ -689,7 +745,7 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
                                           false, st, Role::Transfer);
     }
     mark(2, st);
-    coupling_block<F, C>(op, trans, rb, op.tune_kc, xhat, yhat, st);
+    coupling_block<F, C>(op, trans, rb, op.tune_kc, xhat, yhat, st, w.xt, w.yt);
     mark(3, st);
     // backward transformation: column products over the panels (row panels of
     // single children were measured slower for these small matrices)
@@ -706,18 +762,59 @@ static void product_block(Op &op, int trans, double alpha, const double *x, int6
     mark(8, st);
 }
 
+// Work vectors of the operator for nrhs right-hand sides in blocks of rb.
+static Work op_work(Op &op, int nrhs, int rb)
+{
+    if (nrhs == 1) return Work{op.xp.as<double>(), op.yp.as<double>(), op.ypn.as<double>(), op.xhat.p, op.yhat.p,
+                               true, true, op.xt.as<double>(), op.yt.as<double>()};
+    ensure_block_buffers(op, rb);
+    return Work{op.xpb.as<double>(), op.ypb.as<double>(), op.ypbn.as<double>(), op.xhatb.p, op.yhatb.p, false,
+                true, op.xtb.as<double>(), op.ytb.as<double>()};
+}
+
+// Layout of the work vectors for blocks of rb right-hand sides (rb = 1: one
+// vector) in a buffer at base (NULL: sizes only); returns the bytes used.
+static size_t work_layout(const Op &op, int rb, char *base, Work *w)
+{
+    const int64_t nmax = std::max(op.nrows, op.ncols);
+    const int64_t hmax = std::max<int64_t>(std::max(op.rowb->hat_total, op.colb->hat_total), 1);
+    const size_t fsz = basis_size(op.params.farfield_dtype);
+    const int k = op.params.order_m * op.params.order_m * op.params.order_m;
+    const int64_t kc = op.rowb->has_proj
+                           ? (int64_t)k * std::max(op.rowb->tree->nclusters(), op.colb->tree->nclusters())
+                           : 0;
+    const size_t sizes[7] = {sizeof(double) * nmax * rb, sizeof(double) * nmax * rb, sizeof(double) * nmax * rb,
+                             fsz * hmax * rb, fsz * hmax * rb, sizeof(double) * kc * rb, sizeof(double) * kc * rb};
+    size_t off[7], at = 0;
+    for (int i = 0; i < 7; ++i) {
+        off[i] = at;
+        at += (sizes[i] + 255) & ~size_t(255);
+    }
+    if (base && w)
+        *w = Work{reinterpret_cast<double *>(base + off[0]), reinterpret_cast<double *>(base + off[1]),
+                  reinterpret_cast<double *>(base + off[2]), base + off[3], base + off[4], false, false,
+                  kc ? reinterpret_cast<double *>(base + off[5]) : nullptr,
+                  kc ? reinterpret_cast<double *>(base + off[6]) : nullptr};
+    return at;
+}
+
 template <typename F, typename C>
 static void product(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
-                    int nrhs, hipStream_t st)
+                    int nrhs, hipStream_t st, char *scratch_base)
 {
+    const int rb = nrhs == 1 ? 1 : block_width(op, nrhs);
+    Work w{};
+    if (scratch_base)
+        work_layout(op, rb, scratch_base, &w);
+    else
+        w = op_work(op, nrhs, rb);
     if (nrhs == 1) {
-        product_one<F, C>(op, trans, alpha, x, y, st);
+        product_one<F, C>(op, w, trans, alpha, x, y, st);
         return;
     }
-    const int rb = block_width(op, nrhs);
-    ensure_block_buffers(op, rb);
     for (int c = 0; c < nrhs; c += rb)
-        product_block<F, C>(op, trans, alpha, x + c * ldx, ldx, y + c * ldy, ldy, std::min(rb, nrhs - c), rb, st);
+        product_block<F, C>(op, w, trans, alpha, x + c * ldx, ldx, y + c * ldy, ldy, std::min(rb, nrhs - c), rb,
+                            st);
 }
 
 void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
@@ -742,16 +839,25 @@ void prepare_product(Op &op, int nrhs)
     if (nrhs > 1) ensure_block_buffers(op, block_width(op, nrhs));
 }
 
+void reserve_block_buffers(Op &op) { ensure_block_buffers(op, 64); }
+
+static void dispatch_product(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y,
+                             int64_t ldy, int nrhs, hipStream_t st, char *scratch_base)
+{
+    switch (op.params.farfield_dtype) {
+    case H2B_F64: product<double, double>(op, trans, alpha, x, ldx, y, ldy, nrhs, st, scratch_base); break;
+    case H2B_F32: product<float, float>(op, trans, alpha, x, ldx, y, ldy, nrhs, st, scratch_base); break;
+    default: product<float, bf16_t>(op, trans, alpha, x, ldx, y, ldy, nrhs, st, scratch_base); break;
+    }
+}
+
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st)
 {
     check_product_args(op, trans, x, ldx, y, ldy, nrhs);
-    switch (op.params.farfield_dtype) {
-    case H2B_F64: product<double, double>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
-    case H2B_F32: product<float, float>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
-    default: product<float, bf16_t>(op, trans, alpha, x, ldx, y, ldy, nrhs, st); break;
-    }
+    dispatch_product(op, trans, alpha, x, ldx, y, ldy, nrhs, st, nullptr);
 }
+
 
 // Autotuner of the many-right-hand-side coupling product: times every block
 // width rb in {16, 32, 64} (and, on matrix cores, staging depth kc in {32, 64})
@@ -834,19 +940,23 @@ void op_stats(const Op &op, h2b_op_stats &s)
     s.nfar = (int64_t)op.blocks->far_t.size();
     s.nnear = (int64_t)op.blocks->near_t.size();
     s.near_entries = op.near.total;
-    s.coupling_entries = op.cpl.total;
+    s.coupling_entries = op.recompute ? 0 : op.cpl.total;
+    s.coupling_evals = op.recompute ? op.cpl.total : 0;
     s.row_basis_entries = op.rowb->leaf.total + op.rowb->trans.total;
     s.col_basis_entries = (op.colb == op.rowb) ? 0 : op.colb->leaf.total + op.colb->trans.total;
     s.bytes_near = op.near.total * 8;
     s.bytes_far = s.coupling_entries * (int64_t)coupling_size(op.params.farfield_dtype) +
                   (s.row_basis_entries + s.col_basis_entries) * (int64_t)basis_size(op.params.farfield_dtype);
-    s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.ypn.bytes + op.xhat.bytes + op.yhat.bytes);
+    if (op.rowb->has_proj)
+        s.bytes_far += 8 * (op.rowb->proj.total + (op.colb == op.rowb ? 0 : op.colb->proj.total));
+    s.bytes_vectors = (int64_t)(op.xp.bytes + op.yp.bytes + op.ypn.bytes + op.xhat.bytes + op.yhat.bytes +
+                                op.xt.bytes + op.yt.bytes);
     if (op.sym) {
         s.near_sym_entries = op.sym->P.total;
         s.near_sym_columns = op.sym->col_base.back();
         s.near_sym_corrections = op.sym->ncorr;
     }
-    s.bytes_transposed = op.has_R ? op.near_R.total * 8 + op.cpl_R.total *
+    s.bytes_transposed = op.has_R ? op.near_R.total * 8 + (op.recompute ? 0 : op.cpl_R.total) *
                                                               (int64_t)coupling_size(op.params.farfield_dtype)
                                   : 0;
     s.row_coeffs = op.rowb->hat_total;
@@ -932,7 +1042,16 @@ static void partial_product(Op &op, const double *vp, F *a, hipStream_t st)
     F *xhat = op.xhat.as<F>();
     forward<F>(B, vp, xhat, st);
     launch_fill_zero<F>(a, B.hat_total, st);
-    launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, a, true, st, Role::Coupling);
+    bool done = false;
+    if constexpr (std::is_same<F, double>::value) {
+        if (op.recompute) {  // interpolation bases (no projections)
+            recompute_coupling(op, 0, 1, xhat, a, nullptr, nullptr, st);
+            done = true;
+        }
+    }
+    if (!done)
+        launch_rowpanel<C, F, F>(op.cpl, 0, op.cpl.ngroups(), op.cpl_vals.as<C>(), xhat, a, true, st,
+                                 Role::Coupling);
     for (auto &s : B.bw_steps)
         launch_colpanel<F, F, F>(B.trans_T, s.first, s.second, B.trans_vals.as<F>(), a, a, st, Role::Transfer);
 }
@@ -964,8 +1083,8 @@ void slp_shape_grad(Op &op, const double *x, const double *y, double *gx, double
                     hipStream_t st)
 {
     if (op.kernel != H2B_SLP) fail(H2B_EINVAL, "the shape gradient is implemented for the single-layer matrix");
-    if (op.params.recompress_tol > 0.0)
-        fail(H2B_ENOTSUP, "the shape gradient needs the interpolation bases (recompress_tol = 0)");
+    if (op.params.recompress_tol > 0.0 || op.params.gca_tol > 0.0)
+        fail(H2B_ENOTSUP, "the shape gradient needs the interpolation bases (recompress_tol = 0, gca_tol = 0)");
     if (!x || !y || !gx || !gy || !gz) fail(H2B_EINVAL, "NULL vector");
     switch (op.params.farfield_dtype) {
     case H2B_F64: shape_grad_impl<double, double>(op, x, y, gx, gy, gz, st); break;

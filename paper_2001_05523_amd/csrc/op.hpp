@@ -34,21 +34,28 @@ struct Basis {
     DevMem axes;                            // Chebyshev points, 3*m per cluster
     DevMem perm_mem;
     const int32_t *perm_dev = nullptr;
+    // Coupling evaluated on the fly after recompression: P_c (k'_c x k) per
+    // cluster, rows at the cluster's coefficients, columns at c * k of the
+    // interpolation coefficients.
+    RowPanels proj;
+    ColPanels proj_T;
+    DevMem proj_vals;
+    bool has_proj = false;
 };
 
 // Nearfield of G on one cluster tree stored once per pair of leaves: for every
 // row leaf t the panel [N_tt | N_ts for the nearfield leaves s > t].  The
 // product reads each off-diagonal block once for both y_t += N_ts x_s and
-// y_s += N_ts^T x_t; the column sums go to `scratch` and are added per leaf by
+// y_s += N_ts^T x_t; the column sums go to `colsum` and are added per leaf by
 // a second launch, which also applies the sparse correction of the touching
 // pairs across leaves, whose two quadratures agree only to quadrature error
 // (G_ji - G_ij, stored for G x by row j and for G^T x by row i).
 struct SymNear {
     RowPanels P;                    // groups = row leaves, segment 0 = the diagonal block
     DevMem vals;
-    DevMem scratch;                 // one column sum per panel column
-    std::vector<int64_t> col_base;  // first scratch entry of each group
-    ColPanels red;                  // per leaf u: the blocks (t, u), t != u, as scratch offsets
+    DevMem colsum;                  // one column sum per panel column
+    std::vector<int64_t> col_base;  // first colsum entry of each group
+    ColPanels red;                  // per leaf u: the blocks (t, u), t != u, as colsum offsets
     // copy of the stored blocks out of the full nearfield
     std::vector<int64_t> cp_src, cp_dst;
     std::vector<int32_t> cp_src_ld, cp_dst_ld, cp_rows, cp_cols;
@@ -88,6 +95,12 @@ struct Op {
     DevMem xp, yp, xhat, yhat;              // product work vectors
     DevMem ypn;                             // near-field output (summed with yp by the scatter)
     DevMem xpb, ypb, xhatb, yhatb, ypbn;    // block work vectors (many right-hand sides)
+    // params.recompute_coupling: no coupling values are stored; the coupling
+    // product evaluates S_ts (cpl / cpl_R give the blocks with rank-k
+    // offsets), through the interpolation coefficients xt, yt (k per cluster)
+    // when the bases were recompressed
+    bool recompute = false;
+    DevMem xt, yt, xtb, ytb;
     // The near field runs on its own stream beside the far field: forked
     // after the gather, joined before the scatter.
     hipStream_t side = nullptr;
@@ -140,6 +153,14 @@ void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t 
 // Transposed copies of the leaf and transfer values (after they are final).
 void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);
+// Coupling evaluated on the fly: structure of the transposed grouping.
+void setup_recompute(Op &op, hipStream_t st);
+// Projections P_c of a recompressed basis for the evaluated coupling.
+void set_projection(Basis &B, int k, const std::vector<std::vector<double>> &P, hipStream_t st);
+// yhat += op(S) xhat over every farfield block, S evaluated; rb = 1 or the
+// block width; xt, yt: interpolation-coefficient work vectors (projections only).
+void recompute_coupling(const Op &op, int trans, int rb, const double *xhat, double *yhat, double *xt, double *yt,
+                        hipStream_t st);
 // (Re)builds the transposed copies from the current nearfield and coupling values.
 void make_transposed_copies(Op &op, hipStream_t st);
 // Structure (first call) and values of the once-per-pair nearfield of G.
@@ -150,6 +171,9 @@ void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, c
                         int nrhs);
 // Allocates what a product with nrhs right-hand sides needs (before a capture).
 void prepare_product(Op &op, int nrhs);
+// Block work vectors at the widest block (64 columns): a graph that captured
+// them stays valid, since no later product or tuning has to reallocate them.
+void reserve_block_buffers(Op &op);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);
 // Nodes the next work captured on st will depend on, and their replacement
@@ -158,12 +182,28 @@ void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, doubl
 std::vector<hipGraphNode_t> capture_tail(hipStream_t st);
 void set_capture_tail(hipStream_t st, std::vector<hipGraphNode_t> deps);
 
+// Merged batch: one launch per step for all operators (batch_merged.hip).
+struct MergedBatch;
+struct MergedBatchDeleter {
+    void operator()(MergedBatch *m) const;
+};
+using MergedPtr = std::unique_ptr<MergedBatch, MergedBatchDeleter>;
+// NULL if the products cannot share one program (different far-field types,
+// directions or numbers of right-hand sides, evaluated couplings, A^T x
+// without transposed copies).
+MergedPtr merged_create(int nops, Op *const *ops, const int *trans, const double *alpha, const double *const *x,
+                        const int64_t *ldx, double *const *y, const int64_t *ldy, const int *nrhs, hipStream_t st);
+// Queues the merged products on st (which must be capturing).
+void merged_capture(MergedBatch &m, hipStream_t st);
+int64_t merged_launches(const MergedBatch &m);
+
 // A captured batch of products (one graph, one forked stream per operator).
 struct Batch {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    MergedPtr merged;  // the merged program, or NULL for a graph of per-operator products
     ~Batch();
 };
 std::unique_ptr<Batch> batch_create(int nops, Op *const *ops, const int *trans, const double *alpha,
@@ -185,6 +225,8 @@ void mass_matvec(Op &op, int trans, double alpha, const double *x, double *y, hi
 void hypersingular_matvec(Op &G, double alpha, const double *x, double *y, hipStream_t st);
 // Allocates what hypersingular_matvec needs (before a capture).
 void prepare_hypersingular(Op &G);
+// gy = G y and *out = x^T gy (device scalar), the single-layer bilinear form.
+void slp_bilinear(Op &G, const double *x, const double *y, double *gy, double *out, hipStream_t st);
 // Conjugate gradients for A x = b with the H^2 product of A (or W x = b).
 void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_cg_result &res, double *history,
               hipStream_t st);

@@ -28,18 +28,39 @@ namespace h2b {
 
 // ------------------------------------------------------- device memory
 
+// Device memory comes from the allocator installed with h2b_set_allocator
+// (e.g. the caller's caching allocator), else from hipMalloc.  Each block
+// remembers the allocator that produced it and returns to it.
+struct DeviceAllocator {
+    h2b_alloc_fn alloc = nullptr;  // NULL: hipMalloc / hipFree
+    h2b_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+DeviceAllocator current_allocator();
+void set_allocator(const DeviceAllocator &a);
+// Stream passed to the allocator for allocations made by the calling thread
+// (the stream of the library call in progress).
+hipStream_t alloc_stream();
+struct AllocStreamScope {
+    hipStream_t saved;
+    explicit AllocStreamScope(hipStream_t st);
+    ~AllocStreamScope();
+};
+
 struct DevMem {
     void *p = nullptr;
     size_t bytes = 0;
+    DeviceAllocator a{};
     DevMem() = default;
     DevMem(const DevMem &) = delete;
     DevMem &operator=(const DevMem &) = delete;
-    DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes), a(o.a) { o.p = nullptr; o.bytes = 0; }
     DevMem &operator=(DevMem &&o) noexcept
     {
         release();
         p = o.p;
         bytes = o.bytes;
+        a = o.a;
         o.p = nullptr;
         o.bytes = 0;
         return *this;
@@ -47,7 +68,17 @@ struct DevMem {
     ~DevMem() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (a.free) {
+                // work queued on any stream may still use the block; hipFree
+                // waits for the device, and so does the return to the caller's
+                // allocator, which may hand the block out again at once
+                (void)hipDeviceSynchronize();
+                a.free(p, alloc_stream(), a.ctx);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -55,7 +86,16 @@ struct DevMem {
     {
         release();
         if (n == 0) n = 256;
-        if (hipMalloc(&p, n) != hipSuccess) {
+        a = current_allocator();
+        if (a.alloc) {
+            p = a.alloc(n, alloc_stream(), a.ctx);
+            if (!p) fail(H2B_ENOMEM, "the installed allocator returned NULL for " + std::to_string(n) + " bytes");
+            if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+                a.free(p, alloc_stream(), a.ctx);
+                p = nullptr;
+                fail(H2B_EINVAL, "the installed allocator returned memory that is not 256-byte aligned");
+            }
+        } else if (hipMalloc(&p, n) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
             fail(H2B_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");

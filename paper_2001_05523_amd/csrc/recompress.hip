@@ -585,6 +585,22 @@ void recompress_op(Op &op, double tol, hipStream_t st)
         transpose_basis_values(B, op.params.farfield_dtype, st);
     }
 
+    if (op.recompute) {
+        // couplings evaluated on the fly: keep the rank-k block structure
+        // (cluster c's interpolation coefficients at c * k) and store the
+        // projections P_c = B_c R_c onto the interpolation bases instead
+        for (size_t bi = 0; bi < bases.size(); ++bi) {
+            const Ortho &o = orth[bi];
+            std::vector<std::vector<double>> P(o.kk.size());
+            parallel_for((int64_t)o.kk.size(), [&](int64_t c) {
+                P[c].assign((size_t)o.kk[c] * k, 0.0);
+                if (o.kk[c] > 0) gemm_nn(o.kk[c], k, o.r[c], o.B[c].data(), o.R[c].data(), P[c].data());
+            });
+            set_projection(*bases[bi], k, P, st);
+        }
+        return;
+    }
+
     // 5. S'' = B_t S~ B_s^T
     RowPanels cplN;
     Sandwich sw2;

@@ -12,7 +12,7 @@
 // which makes the result equal to the full nearfield product.
 //
 // Launches of one product: k_nearsym (rows: y_t; columns: one sum per panel
-// column into a scratch vector), then k_symreduce (per leaf u: the column sums
+// column into a column-sum vector), then k_symreduce (per leaf u: the column sums
 // of the blocks (t, u), t != u, plus the corrections of u's rows).
 #include <hip/hip_runtime.h>
 
@@ -57,7 +57,7 @@ __device__ inline int find_seg(const int32_t *c0, int n, int col)
 // per-lane predicates; the products feed the row sums (wave reductions) and,
 // weighted by x_t of the two rows, the column sums in LDS (ds_add_f64).
 // Column sums of the diagonal block go to y_t for G^T x and are dropped for
-// G x; the others go to the scratch vector.
+// G x; the others go to the column-sum vector.
 template <bool TRANS>
 __global__ __launch_bounds__(SYM_NW * 64) void k_nearsym(RowPanelDev d, int chunk, const double *__restrict__ vals,
                                                          const double *__restrict__ x, double *__restrict__ y,
@@ -296,7 +296,7 @@ void build_structure(const Op &op, SymNear &S)
     S.col_base.resize(S.P.ngroups() + 1, 0);
     for (int g = 0; g < S.P.ngroups(); ++g) S.col_base[g + 1] = S.col_base[g] + S.P.ncols[g];
 
-    // reduction lists: per leaf u (group order) the scratch offsets of (t, u), t != u
+    // reduction lists: per leaf u (group order) the column-sum offsets of (t, u), t != u
     std::vector<std::vector<int64_t>> per_leaf(ncl);
     for (int g = 0; g < S.P.ngroups(); ++g)
         for (int k = S.P.seg_ptr[g] + 1; k < S.P.seg_ptr[g + 1]; ++k)
@@ -396,7 +396,7 @@ void make_symmetric_near(Op &op, hipStream_t st)
         pk.add(S->cb_b, const_cast<int64_t **>(&S->d_cb_b));
         pk.upload(S->desc, st);
         S->vals.alloc(sizeof(double) * std::max<int64_t>(S->P.total, 1));
-        S->scratch.alloc(sizeof(double) * std::max<int64_t>(S->col_base.back(), 1));
+        S->colsum.alloc(sizeof(double) * std::max<int64_t>(S->col_base.back(), 1));
         S->cf_val.alloc(sizeof(double) * std::max<int64_t>(S->ncorr, 1));
         S->cb_val.alloc(sizeof(double) * std::max<int64_t>(S->ncorr, 1));
         // host copies of what the kernels read from the descriptors are no longer needed
@@ -432,7 +432,7 @@ void symmetric_near_product(const Op &op, int trans, const double *xp, double *y
     const int chunk = std::min(SYM_CHUNK, std::max(64, (S.P.max_ncols + 63) / 64 * 64));
     if (chunk < S.P.max_nrows) fail(H2B_EINVAL, "column chunk smaller than a leaf");
     const size_t shm = sizeof(double) * (2 * (size_t)chunk + 64);
-    double *cs = S.scratch.as<double>();
+    double *cs = S.colsum.as<double>();
     if (trans)
         hipLaunchKernelGGL(k_nearsym<true>, dim3(ng), dim3(SYM_NW * 64), shm, st, S.P.dev, chunk,
                            S.vals.as<double>(), xp, ypn, cs, S.d_col_base);

@@ -104,15 +104,33 @@ def test_gca_error_falls_with_the_tolerance():
 
 
 def test_gca_mixed_precision_and_arguments():
-    """FP32 far field: the product stays within 1e-5 of the FP64 one; GCA
-    together with recompression is refused."""
+    """The cross-approximation bases are not orthonormal, so an FP32 or BF16
+    far field on them is refused (H2B_ENOTSUP); GCA together with
+    recompression is refused as a contradictory request (H2B_EINVAL)."""
     h = _lib()
     v, t = synth.octa_sphere(16)
-    x = synth.random_vector(len(t), 91)
-    y64 = _product(h.Operator(v, t, kernel="slp", leaf=32, order_m=4, q_near=4, gca_tol=1e-6), x)
-    y32 = _product(h.Operator(v, t, kernel="slp", leaf=32, order_m=4, q_near=4, gca_tol=1e-6,
-                              farfield_dtype="f32"), x)
-    assert _rel(y32, y64) <= 1e-5
+    for kernel in ("slp", "dlp"):
+        for dt in ("f32", "bf16"):
+            with pytest.raises(h.H2BError) as e:
+                h.Operator(v, t, kernel=kernel, leaf=32, order_m=4, q_near=4, gca_tol=1e-6, farfield_dtype=dt)
+            assert e.value.code == h.H2B_ENOTSUP
     with pytest.raises(h.H2BError) as e:
         h.Operator(v, t, kernel="slp", leaf=32, order_m=3, q_near=4, gca_tol=1e-4, recompress_tol=1e-6)
     assert e.value.code == h.H2B_EINVAL
+
+
+def test_gca_operator_refuses_shape_derivatives():
+    """The shape derivative differentiates the tensor Lagrange polynomials of
+    the interpolation bases; cross-approximation bases are pivot-based, so
+    both the geometry update and the gradient refuse them (H2B_ENOTSUP)."""
+    import torch
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    op = h.Operator(v, t, kernel="slp", leaf=16, order_m=2, q_near=4, gca_tol=1e-4)
+    x = torch.ones(len(t), dtype=torch.float64, device="cuda")
+    with pytest.raises(h.H2BError) as e:
+        op.shape_grad(x, x)
+    assert e.value.code == h.H2B_ENOTSUP
+    with pytest.raises(h.H2BError) as e:
+        op.set_geometry(v)
+    assert e.value.code == h.H2B_ENOTSUP

@@ -180,7 +180,9 @@ def test_cg_h2_solution_matches_oracle_h2():
 def test_cg_paper_functions_converge_first_order():
     """Section 5 (L2 error of the Dirichlet-to-Neumann problem): the L2 error
     of the Neumann data of u1, u2, u3 falls at the rate O(h) from s = 8 to 64
-    (n = 512 .. 32,768), CG to 1e-9.  As in the paper, the accuracy of the
+    (n = 512 .. 32,768), CG to 1e-9, and the discrete H^{-1/2} error (the
+    G-energy of the P0 projection of the exact data minus the solution,
+    through h2b_slp_bilinear) falls like O(h^2), as the paper reports.  As in the paper, the accuracy of the
     matrix approximation has to grow as h shrinks: the interpolation order
     rises with the mesh (m = 4 recompressed to 1e-6 for s <= 16, then m = 5
     and 6; with m = 4 at s = 64 the error of u2 grows instead of halving).
@@ -191,6 +193,7 @@ def test_cg_paper_functions_converge_first_order():
     h = _lib()
     torch = _torch()
     errs = {name: [] for name in krylov.TEST_FUNCTIONS}
+    energy = {name: [] for name in krylov.TEST_FUNCTIONS}
     for s, m in ((8, 4), (16, 4), (32, 5), (64, 6)):
         v, t = synth.octa_sphere(s)
         print("dtn s=%d m=%d" % (s, m), flush=True)
@@ -204,16 +207,30 @@ def test_cg_paper_functions_converge_first_order():
             assert r["status"] == "converged", (s, name, r)
             e = krylov.neumann_l2_error(v, t, _host(x), grad)
             errs[name].append(e)
+            # discrete H^{-1/2} error: the G-energy of Pi t - t_h through the
+            # library's bilinear form
+            d = _dev(krylov.neumann_projection(v, t, grad)) - x
+            gd = torch.empty_like(d)
+            val = torch.zeros((), dtype=torch.float64, device="cuda")
+            h._check(h.h2b_slp_bilinear(G.handle, h._vp(d.data_ptr()), h._vp(d.data_ptr()), h._vp(gd.data_ptr()),
+                                        h._vp(val.data_ptr()), None))
+            torch.cuda.synchronize()
+            energy[name].append(math.sqrt(float(val)))
             if s <= 16:
                 Gd, Kd, M = _oracle_dtn(s)
                 eo = krylov.neumann_l2_error(v, t, krylov.dtn_solve(Gd, Kd, M, u(v)), grad)
                 assert abs(e - eo) <= 2e-2 * eo, (s, name, e, eo)
     print(errs)
+    print("discrete H^-1/2 errors", energy)
     for name, e in errs.items():
         assert all(e[i] > e[i + 1] for i in range(3)), (name, e)
         for i in (1, 2):
             rate = math.log2(e[i] / e[i + 1])
             assert 0.8 <= rate <= 1.6, (name, e, rate)
+    for name, e in energy.items():
+        assert all(e[i] > e[i + 1] for i in range(3)), (name, e)
+        rate = math.log2(e[2] / e[3])
+        assert 1.4 <= rate <= 2.8, (name, e, rate)
 
 
 def test_cg_mixed_precision_far_field():

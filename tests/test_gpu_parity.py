@@ -228,20 +228,20 @@ def test_recompressed_mixed_precision():
             assert d <= 1e-5
 
 
-def test_mixed_precision_far_field():
-    """FP32 bases and coupling matrices with FP32 accumulation; near field FP64.
-    Relative difference to the FP64 product <= 1e-5."""
+def test_reduced_precision_needs_orthonormal_bases():
+    """FP32 and BF16 far fields are refused (H2B_ENOTSUP) where the bases are
+    not orthonormal: plain interpolation (recompress_tol = 0) and the Green
+    cross approximation.  Their rounding would be amplified by the basis
+    condition beyond the 1e-5 of the precision form."""
     h = _lib()
-    v, t = synth.octa_sphere(16)
+    v, t = synth.octa_sphere(4)
     for kernel in ("slp", "dlp"):
-        op64 = h.Operator(v, t, kernel=kernel, leaf=16, order_m=4, q_near=4)
-        op32 = h.Operator(v, t, kernel=kernel, leaf=16, order_m=4, q_near=4, farfield_dtype="f32")
-        for trans in (False, True):
-            nin = op64.shape[0] if trans else op64.shape[1]
-            x = synth.random_vector(nin, 11)
-            y64 = _run(op64, x, trans=trans)
-            y32 = _run(op32, x, trans=trans)
-            assert np.linalg.norm(y32 - y64) / np.linalg.norm(y64) <= 1e-5
+        for dt in ("f32", "bf16"):
+            for kw in (dict(), dict(gca_tol=1e-4)):
+                with pytest.raises(h.H2BError) as e:
+                    h.Operator(v, t, kernel=kernel, leaf=8, order_m=3, q_near=4, farfield_dtype=dt, **kw)
+                assert e.value.code == h.H2B_ENOTSUP, (kernel, dt, kw)
+            h.Operator(v, t, kernel=kernel, leaf=8, order_m=3, q_near=4, farfield_dtype=dt, recompress_tol=1e-6)
 
 
 def test_multiple_right_hand_sides():
@@ -436,7 +436,8 @@ def test_batched_graph_of_uneven_meshes():
             a, b, c = rng.uniform(0.5, 2.0, size=3)
             v, t = synth.ellipsoid(s, a, b, c)
         kern = "slp" if k % 3 else "dlp"
-        op = h.Operator(v, t, kernel=kern, leaf=16, order_m=3, q_near=4, farfield_dtype="f32")
+        op = h.Operator(v, t, kernel=kern, leaf=16, order_m=3, q_near=4, farfield_dtype="f32",
+                        recompress_tol=1e-6)
         x = torch.tensor(synth.random_vector(op.shape[1], 303 + k), device="cuda")
         y = torch.zeros(op.shape[0], dtype=torch.float64, device="cuda")
         ref = torch.zeros_like(y)
@@ -471,3 +472,83 @@ def test_batch_rejects_repeated_operator():
     y2 = torch.zeros_like(x)
     with pytest.raises(h.H2BError):
         h.Batch([(op, x, y1), (op, x, y2)])
+
+
+@pytest.mark.parametrize("nrhs", [64, 37])
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_block_product_against_oracle_h2(kernel, nrhs):
+    """Blocks of right-hand sides in FP64 (block GEMMs, nearfield and coupling
+    on matrix cores) against the oracle's dense H^2 matrix times the same
+    block, element by element to rounding, for A X and A^T X; the mesh spans
+    many leaves and the 37-column block leaves a ragged tail of the 64-wide
+    block."""
+    h = _lib()
+    s, leaf, m = 16, 16, 4
+    v, t = synth.octa_sphere(s)
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=m, q_near=4)
+    A = _dense(s, kernel, 4)
+    H, _ = h2.h2_dense(v, t, kernel, leaf, m, near_matrix=A)
+    for trans in (False, True):
+        nin = A.shape[0] if trans else A.shape[1]
+        X = synth.random_vector(nin, 381 + trans, cols=nrhs)
+        Y = _run_block(op, X, trans=trans, alpha=0.5)
+        ref = 0.5 * ((H.T if trans else H) @ X)
+        assert np.max(np.abs(Y - ref)) <= 1e-11 * np.max(np.abs(ref)), (trans, _maxrel(Y, ref))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_recompressed_block_product_against_oracle_h2(dtype):
+    """Recompressed order-4 operators (orthonormal bases) with FP64, FP32 and
+    BF16 far fields, 64 right-hand sides, against the oracle's dense
+    (uncompressed) H^2 matrix: every column within the recompression bound
+    (20 x 1e-6) plus the rounding of the storage type (FP32 1e-5, BF16 5e-3)."""
+    h = _lib()
+    s, leaf = 16, 16
+    v, t = synth.octa_sphere(s)
+    for kernel in ("slp", "dlp"):
+        op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=4, q_near=4, recompress_tol=1e-6,
+                        farfield_dtype=dtype)
+        A = _dense(s, kernel, 4)
+        H, _ = h2.h2_dense(v, t, kernel, leaf, 4, near_matrix=A)
+        bound = 20e-6 + {"f64": 0.0, "f32": 1e-5, "bf16": 5e-3}[dtype]
+        for trans in (False, True):
+            nin = A.shape[0] if trans else A.shape[1]
+            X = synth.random_vector(nin, 391 + trans, cols=64)
+            Y = _run_block(op, X, trans=trans)
+            ref = (H.T if trans else H) @ X
+            err = np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            print("%s %s trans=%d: max column error %.3e" % (kernel, dtype, trans, err.max()))
+            assert err.max() <= bound, (kernel, trans, err.max())
+
+
+def test_batch_survives_tuning_after_creation():
+    """A batch captures the block work vectors of its operators; tuning an
+    operator afterwards (which selects another block width) and wider
+    products must not move them, so the replays still equal eager
+    products."""
+    torch = _torch()
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    ops = [h.Operator(v, t, kernel=k, leaf=16, order_m=3, q_near=4) for k in ("slp", "dlp")]
+    items, refs = [], []
+    for i, op in enumerate(ops):
+        X = torch.tensor(synth.random_vector(op.shape[1], 395 + i, cols=16), device="cuda").t().contiguous().t()
+        Y = torch.zeros((16, op.shape[0]), dtype=torch.float64, device="cuda").t()
+        R = torch.zeros((16, op.shape[0]), dtype=torch.float64, device="cuda").t()
+        op.matvec(X, R)
+        items.append((op, X, Y))
+        refs.append(R)
+    batch = h.Batch(items)
+    for op in ops:
+        op.tune(64)
+        Xw = torch.tensor(synth.random_vector(op.shape[1], 397, cols=64), device="cuda").t().contiguous().t()
+        op.matvec(Xw, torch.zeros((64, op.shape[0]), dtype=torch.float64, device="cuda").t())
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for _, _, Y in items:
+            Y.zero_()
+        batch.launch()
+        torch.cuda.synchronize()
+        for (_, _, Y), R in zip(items, refs):
+            np.testing.assert_allclose(Y.cpu().numpy(), R.cpu().numpy(), rtol=0,
+                                       atol=1e-12 * float(R.abs().max()))

@@ -121,6 +121,74 @@ def test_invalid_tree_and_block_arguments():
         h.Blocks(R, other, 1.0)
 
 
+def _assemble_status(h, blocks, kernel, **kw):
+    p = h.default_params(**kw)
+    out = ctypes.c_void_p()
+    return h.h2b_assemble(blocks.handle, kernel, ctypes.byref(p), None, ctypes.byref(out))
+
+
+def test_assembly_arguments_rejected_on_the_host():
+    """Requests that assembly refuses before any device call: the
+    single-layer matrix on two different triangle trees (its column basis is
+    the row basis), an FP32 or BF16 far field on non-orthonormal bases
+    (interpolation without recompression, cross approximation), parameters
+    out of range."""
+    h = _lib()
+    v, t = synth.octa_sphere(4)
+    m = h.Mesh(v, t)
+    R = h.Tree(m, 0, 8)
+    R2 = h.Tree(m, 0, 16)
+    C = h.Tree(m, 1, 8)
+    assert _assemble_status(h, h.Blocks(R, R2, 1.0), h.H2B_SLP) == h.H2B_EINVAL
+    assert b"one cluster tree" in h.h2b_last_error()
+    assert _assemble_status(h, h.Blocks(R2, R, 1.0), h.H2B_SLP) == h.H2B_EINVAL
+    B = h.Blocks(R, R, 1.0)
+    BK = h.Blocks(R, C, 1.0)
+    for dt in (h.H2B_F32, h.H2B_BF16):
+        for blk, ker in ((B, h.H2B_SLP), (BK, h.H2B_DLP)):
+            assert _assemble_status(h, blk, ker, farfield_dtype=dt) == h.H2B_ENOTSUP
+            assert _assemble_status(h, blk, ker, farfield_dtype=dt, gca_tol=1e-4) == h.H2B_ENOTSUP
+            assert b"orthonormal" in h.h2b_last_error()
+    assert _assemble_status(h, B, h.H2B_SLP, gca_tol=1e-4, recompress_tol=1e-6) == h.H2B_EINVAL
+    assert _assemble_status(h, B, h.H2B_SLP, order_m=7) == h.H2B_EINVAL
+    assert _assemble_status(h, B, h.H2B_SLP, q_near=1) == h.H2B_EINVAL
+    assert _assemble_status(h, B, h.H2B_DLP) == h.H2B_EINVAL  # K needs a P1 column tree
+    assert _assemble_status(h, BK, h.H2B_SLP) == h.H2B_EINVAL
+
+
+def test_allocator_failure_gives_enomem():
+    """An installed allocator that returns NULL makes assembly fail with
+    H2B_ENOMEM before any device work, with no handle written; exactly one
+    NULL callback is rejected.  The allocator is restored afterwards."""
+    h = _lib()
+    calls = []
+
+    def alloc(nbytes, stream, ctx):
+        calls.append(nbytes)
+        return None
+
+    def free(ptr, stream, ctx):
+        raise AssertionError("nothing was allocated")
+
+    a, f = h._ALLOC_FN(alloc), h._FREE_FN(free)
+    v, t = synth.octa_sphere(4)
+    m = h.Mesh(v, t)
+    R = h.Tree(m, 0, 8)
+    B = h.Blocks(R, R, 1.0)
+    try:
+        assert h.h2b_set_allocator(a, h._FREE_FN(), None) == h.H2B_EINVAL
+        assert h.h2b_set_allocator(h._ALLOC_FN(), f, None) == h.H2B_EINVAL
+        assert h.h2b_set_allocator(a, f, None) == h.H2B_OK
+        p = h.default_params()
+        out = ctypes.c_void_p()
+        assert h.h2b_assemble(B.handle, h.H2B_SLP, ctypes.byref(p), None, ctypes.byref(out)) == h.H2B_ENOMEM
+        assert out.value is None
+        assert b"returned NULL" in h.h2b_last_error()
+        assert len(calls) == 1 and calls[0] > 0
+    finally:
+        h.use_torch_allocator()
+
+
 def test_null_arguments_rejected():
     h = _lib()
     out = ctypes.c_void_p()

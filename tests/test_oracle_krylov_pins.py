@@ -288,3 +288,43 @@ def test_error_measures_of_exact_data():
         vs, ts = synth.octa_sphere(s)
         errs.append(krylov.dirichlet_l2_error(vs, ts, krylov.u1(vs), krylov.u1))
     assert 1.7 <= math.log2(errs[1] / errs[2]) <= 2.3, errs
+
+
+def test_energy_norm_of_constants_and_exact_data():
+    """The G-norm: on the unit sphere the single-layer potential of the
+    constant density 1 is 1, so 1^T G 1 tends to |S| = 4 pi (the polyhedral
+    mesh misses it by O(h^2): the gap shrinks about fourfold as h halves);
+    the norm is absolutely homogeneous; the energy error of the exact P0
+    Neumann data of a linear function is zero."""
+    gaps = []
+    for s in (4, 8, 16):
+        v, t = synth.octa_sphere(s)
+        G = oracle.slp_dense(v, t, 4)
+        gaps.append(abs(krylov.energy_norm(G, np.ones(len(t))) ** 2 - 4.0 * math.pi))
+    assert gaps[0] > gaps[1] > gaps[2]
+    assert 3.0 <= gaps[1] / gaps[2] <= 5.0, gaps
+    v, t = synth.perturbed_sphere(4, seed=6)
+    G = oracle.slp_dense(v, t, 4)
+    e = synth.random_vector(len(t), 8)
+    assert krylov.energy_norm(G, -2.5 * e) == pytest.approx(2.5 * krylov.energy_norm(G, e), rel=1e-13)
+    _, n, _ = _geom(v, t)
+    a = np.array([0.4, 0.9, -0.3])
+    grad = lambda p: np.broadcast_to(a, p.shape)  # noqa: E731
+    assert krylov.neumann_energy_error(G, v, t, n @ a, grad) <= 1e-12
+
+
+def test_dtn_energy_error_converges_second_order():
+    """Section 5: the discrete H^{-1/2} error (G-norm of the difference between
+    the P0 projection of the exact Neumann data and the Galerkin solution of
+    eq. (matrix_dtn)) falls like O(h^2) for u1, u2 and u3; the observed order
+    between s = 8 and 16 is checked."""
+    errs = {name: [] for name in krylov.TEST_FUNCTIONS}
+    for s in (8, 16):
+        v, t = synth.octa_sphere(s)
+        G, K, M = krylov.dtn_matrices(v, t, 4)
+        for name, (u, grad) in krylov.TEST_FUNCTIONS.items():
+            sol = krylov.dtn_solve(G, K, M, u(v))
+            errs[name].append(krylov.neumann_energy_error(G, v, t, sol, grad))
+    for name, e in errs.items():
+        rate = math.log2(e[0] / e[1])
+        assert 1.6 <= rate <= 2.8, (name, e, rate)
