@@ -276,6 +276,32 @@ h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);
 h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
                       double *y, int64_t ldy, int nrhs, void *hip_stream);
 
+/* Size of the static device array that holds the work vectors of
+ * h2b_matvec_noalloc (128 MiB on every GPU the library runs on, held until
+ * the process ends). */
+#define H2B_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): h2b_matvec with
+ * every work vector of the product (the permuted input and output, the
+ * nearfield output, the cluster coefficients; per block of right-hand sides
+ * for nrhs > 1) placed in a static device array of H2B_NOALLOC_SCRATCH_BYTES
+ * instead of the operator's own vectors.  The call allocates nothing: no
+ * hipMalloc, no installed allocator, no events.  Same arguments, result and
+ * asynchronous behaviour as h2b_matvec, except that the nearfield of G is
+ * read from its full storage (the once-per-pair form needs the operator's
+ * column-sum vector) and no phase timing is recorded.  The work vectors need
+ * 3 max(rows, cols) rb doubles plus 2 max(cluster coefficients) rb far-field
+ * values (rb = 1 for nrhs = 1, else the block width 16, 32 or 64), each
+ * rounded up to 256 bytes; larger requests fail with H2B_EINVAL before any
+ * launch.  Every call on a GPU uses that GPU's one array, which keeps the
+ * contents of the last call: calls that overlap in time on one GPU (on
+ * different streams, or from several threads) race and give wrong results;
+ * order them on one stream.  Errors: as h2b_matvec, and H2B_EINVAL for work
+ * vectors beyond the array. */
+h2b_status h2b_matvec_noalloc(h2b_op op, int trans, double alpha, const double *x, int64_t ldx,
+                              double *y, int64_t ldy, int nrhs, void *hip_stream);
+
 /* Batched products over several operators (e.g. meshes of different sizes):
  * captures y_i += alpha_i op_i(A_i) x_i for i < nops into one HIP graph.  The
  * products of different operators are concurrent branches of the graph; each

@@ -94,6 +94,7 @@ _SIGS = {
     "h2b_op_destroy": ([_vp], ctypes.c_int),
     "h2b_op_info": ([_vp, _P(h2b_op_stats)], ctypes.c_int),
     "h2b_matvec": ([_vp, ctypes.c_int, _dbl, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
+    "h2b_matvec_noalloc": ([_vp, ctypes.c_int, _dbl, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
     "h2b_op_tune": ([_vp, ctypes.c_int, _vp, _P(_dbl)], ctypes.c_int),
     "h2b_batch_create": ([ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _P(_vp)], ctypes.c_int),
     "h2b_batch_launch": ([_vp, _vp], ctypes.c_int),

@@ -286,6 +286,16 @@ h2b_status h2b_matvec(h2b_op op, int trans, double alpha, const double *x, int64
     });
 }
 
+h2b_status h2b_matvec_noalloc(h2b_op op, int trans, double alpha, const double *x, int64_t ldx, double *y,
+                              int64_t ldy, int nrhs, void *hip_stream)
+{
+    return guarded([&] {
+        need(op, "op");
+        h2b::matvec_noalloc(*op->op, trans ? 1 : 0, alpha, x, ldx, y, ldy, nrhs,
+                            static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 h2b_status h2b_batch_create(int nops, const h2b_op *ops, const int *trans, const double *alpha,
                             const double *const *x, const int64_t *ldx, double *const *y,
                             const int64_t *ldy, const int *nrhs, void *hip_stream, h2b_batch *out)

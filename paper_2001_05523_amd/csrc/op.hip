@@ -858,6 +858,46 @@ void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, doubl
     dispatch_product(op, trans, alpha, x, ldx, y, ldy, nrhs, st, nullptr);
 }
 
+// ------------------------------------------- product without allocation
+//
+// Work vectors of h2b_matvec_noalloc: one file-scope device array per GPU,
+// shared by every such call on that GPU.  Host code never uses the array's
+// name as an address (on the host it names a stand-in, not device memory):
+// the device address comes from hipGetSymbolAddress, once per device.
+
+static __device__ __align__(256) unsigned char scratch[H2B_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_ptr;  // per device id; NULL until looked up
+}  // namespace
+
+static char *scratch_address()
+{
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "current device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!ptr) fail(H2B_EDEVICE, "scratch symbol address is NULL");
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+void matvec_noalloc(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+                    int nrhs, hipStream_t st)
+{
+    check_product_args(op, trans, x, ldx, y, ldy, nrhs);
+    const int rb = nrhs == 1 ? 1 : block_width(op, nrhs);
+    const size_t need = work_layout(op, rb, nullptr, nullptr);
+    if (need > (size_t)H2B_NOALLOC_SCRATCH_BYTES)
+        fail(H2B_EINVAL, "the product needs " + std::to_string(need) + " bytes of work vectors, more than the " +
+                             std::to_string((size_t)H2B_NOALLOC_SCRATCH_BYTES) + " of the static scratch array");
+    dispatch_product(op, trans, alpha, x, ldx, y, ldy, nrhs, st, scratch_address());
+}
 
 // Autotuner of the many-right-hand-side coupling product: times every block
 // width rb in {16, 32, 64} (and, on matrix cores, staging depth kc in {32, 64})

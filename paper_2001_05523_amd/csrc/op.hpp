@@ -176,6 +176,9 @@ void prepare_product(Op &op, int nrhs);
 void reserve_block_buffers(Op &op);
 void matvec(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
             int nrhs, hipStream_t st);
+// The same product with its work vectors in the static scratch array (no allocation).
+void matvec_noalloc(Op &op, int trans, double alpha, const double *x, int64_t ldx, double *y, int64_t ldy,
+                    int nrhs, hipStream_t st);
 // Nodes the next work captured on st will depend on, and their replacement
 // (st must be capturing): with these a single captured stream forms parallel
 // branches of the graph.
