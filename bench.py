@@ -90,25 +90,29 @@ def kernel_name(op, phase, info):
     return "%s nearfield, A x and A^T x launches (k_rowpanel<double, double, double, 3, 4, 2>)" % op
 
 
-def time_steps(torch, items, steps, warmup):
+def time_steps(torch, items, steps, warmup, streams=None):
     """Times `steps` passes over items = [(op, x, y, trans), ...] after `warmup`
     untimed passes, with the operators' phase events recorded on the streams
-    the phases run on.  Returns ms per pass and each operator's mean phase
-    times (over its products in the pass)."""
+    the phases run on.  With `streams` (one torch stream per item, or None)
+    the products of different operators are issued on their own streams, so
+    that they may run concurrently; products on one operator share a stream
+    (they share its work vectors).  Returns ms per pass and each operator's
+    mean phase times (over its products in the pass)."""
     ops = []
     for it in items:
         if all(it[0] is not o for o in ops):
             ops.append(it[0])
+    streams = streams or [None] * len(items)
     for _ in range(warmup):
-        for op, x, y, tr in items:
-            op.matvec(x, y, trans=tr)
+        for (op, x, y, tr), s in zip(items, streams):
+            op.matvec(x, y, trans=tr, stream=s)
     torch.cuda.synchronize()
     for op in ops:
         op.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        for op, x, y, tr in items:
-            op.matvec(x, y, trans=tr)
+        for (op, x, y, tr), s in zip(items, streams):
+            op.matvec(x, y, trans=tr, stream=s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phases = [op.phase_times() for op in ops]

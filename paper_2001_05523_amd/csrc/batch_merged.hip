@@ -411,7 +411,6 @@ void merged_far(MergedBatch &m, hipStream_t st)
 void merged_near(MergedBatch &m, hipStream_t st)
 {
     double *xp = m.xp.as<double>(), *ypn = m.ypn.as<double>();
-    launch_fill_zero<double>(ypn, m.nout * m.rb, st);
     if (m.rb == 1)
         launch_rowpanel<double, double, double>(m.near, 0, m.near.ngroups(), m.near_v, xp, ypn, true, st, Role::Near);
     else if (m.near.max_nrows <= 64)
@@ -425,6 +424,7 @@ template <typename F, typename C> void merged_run_t(MergedBatch &m, hipStream_t 
 {
     launch_fill_zero<F>(m.yhat.as<F>(), m.hout * m.rb, st);
     launch_fill_zero<double>(m.yp.as<double>(), m.nout * m.rb, st);
+    launch_fill_zero<double>(m.ypn.as<double>(), m.nout * m.rb, st);
     if (m.nin > 0) {
         hipLaunchKernelGGL(k_gather_abs, dim3(grid_of(m.nin * m.rb)), dim3(BT), 0, st, m.gsrc.as<int64_t>(),
                            m.gld.as<int64_t>(), m.nin, m.nb, m.rb, m.xbase, m.xp.as<double>());

@@ -36,6 +36,13 @@ void launch_near_assemble(h2b_kernel kernel, const RowPanels &rp, const int32_t 
                           const int32_t *cperm, const GeoDev &geo, const QuadDev &quad,
                           double *vals, hipStream_t st);
 
+// Double-layer nearfield with every triangle pair integrated once per row:
+// lst[lptr[g] .. lptr[g + 1]) is the sorted list of the triangles around the
+// column vertices of group g.
+void launch_near_assemble_dlp(const RowPanels &rp, const int64_t *lptr, const int32_t *lst, const int32_t *rperm,
+                              const int32_t *cperm, const GeoDev &geo, const QuadDev &quad, double *vals,
+                              hipStream_t st);
+
 // Leaf bases stored as V_t^T (k x |t| per leaf group of rp).
 // space P0: (V_t)_{i nu} = int_{tau_i} L_{t,nu};
 // dlp_cols (space P1): (W_t)_{j nu} = sum_{tau around j} int_tau phi_j dL_{t,nu}/dn_tau.

@@ -86,4 +86,16 @@ void sym_eig(int n, std::vector<double> &a, std::vector<double> &ev, std::vector
 // Chebyshev points (first kind) per axis of the box of cluster c, m per axis.
 void cheb_axes(const Tree &tr, int c, int m, double *pts /* 3*m */);
 
+// Green cross approximation on one tree (triangles, or the vertices of K's
+// columns): per cluster the rank k_t, the pivots t_hat (original indices,
+// pivot order) and V, the leaf basis
+// (|t| x k_t, position order) or the stacked transfers [E_1; E_2]
+// ((k_1 + k_2) x k_t), both row-major.
+struct GcaBases {
+    std::vector<int> rank;
+    std::vector<std::vector<int32_t>> hat;
+    std::vector<std::vector<double>> V;
+};
+GcaBases gca_bases(const Tree &T, int m, double eps);
+
 }  // namespace h2b

@@ -252,6 +252,92 @@ __device__ double dlp_part(const GeoDev &g, int i, int tj, int slot, const QuadD
     return v * jj;
 }
 
+// The double-layer integrals of a pair for all three barycentric weights of
+// Y at once (corners in quadrature order): the same rules as dlp_touching and
+// pair_regular, sharing every kernel evaluation among the three corners.
+__device__ void dlp_touching3(int ns, const Tri &X, const Tri &Y, const double ny[3], const QuadDev &Q,
+                              double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    if (ns == 3) return;  // x - y lies in the plane of the triangle
+    const int nreg = (ns == 2) ? 5 : 2;
+    for (int r = 0; r < nreg; ++r)
+        for (int i = 0; i < Q.q; ++i)
+            for (int j = 0; j < Q.q; ++j) {
+                const double wij = Q.w[i] * Q.w[j];
+                for (int k = 0; k < Q.q; ++k) {
+                    double xd[2], yd[2];
+                    double jac = ss_dirs(ns, r, Q.t[i], Q.t[j], Q.t[k], xd, yd);
+                    double D0 = xd[0] * X.e1[0] + xd[1] * X.e2[0] - yd[0] * Y.e1[0] - yd[1] * Y.e2[0];
+                    double D1 = xd[0] * X.e1[1] + xd[1] * X.e2[1] - yd[0] * Y.e1[1] - yd[1] * Y.e2[1];
+                    double D2 = xd[0] * X.e1[2] + xd[1] * X.e2[2] - yd[0] * Y.e1[2] - yd[1] * Y.e2[2];
+                    double ir = rsqrt(D0 * D0 + D1 * D1 + D2 * D2);
+                    double kern = (D0 * ny[0] + D1 * ny[1] + D2 * ny[2]) * ir * ir * ir;
+                    const double f = wij * Q.w[k] * jac * kern;
+                    out[0] += f * (0.5 - yd[0] * (1.0 / 3.0));
+                    out[1] += f * ((yd[0] - yd[1]) * (1.0 / 3.0));
+                    out[2] += f * (yd[1] * (1.0 / 3.0));
+                }
+            }
+}
+
+__device__ void pair_regular_dlp3(const Tri &X, const Tri &Y, const double ny[3], const QuadDev &Q, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    for (int i = 0; i < Q.q; ++i) {
+        const double u = Q.t[i];
+        for (int j = 0; j < Q.q; ++j) {
+            const double v = u * Q.t[j];
+            const double wx = Q.w[i] * Q.w[j] * u;
+            const double x0 = X.p[0] + u * X.e1[0] + v * X.e2[0];
+            const double x1 = X.p[1] + u * X.e1[1] + v * X.e2[1];
+            const double x2 = X.p[2] + u * X.e1[2] + v * X.e2[2];
+            double in0 = 0.0, in1 = 0.0, in2 = 0.0;
+            for (int k = 0; k < Q.q; ++k) {
+                const double s = Q.t[k];
+                const double ws = Q.w[k] * s;
+                for (int l = 0; l < Q.q; ++l) {
+                    const double sv = s * Q.t[l];
+                    const double d0 = x0 - (Y.p[0] + s * Y.e1[0] + sv * Y.e2[0]);
+                    const double d1 = x1 - (Y.p[1] + s * Y.e1[1] + sv * Y.e2[1]);
+                    const double d2 = x2 - (Y.p[2] + s * Y.e1[2] + sv * Y.e2[2]);
+                    const double ir = rsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    const double f = (d0 * ny[0] + d1 * ny[1] + d2 * ny[2]) * ir * ir * ir;
+                    const double wsl = ws * Q.w[l];
+                    in0 += wsl * (f * (1.0 - s));
+                    in1 += wsl * (f * (s - sv));
+                    in2 += wsl * (f * sv);
+                }
+            }
+            out[0] += wx * in0;
+            out[1] += wx * in1;
+            out[2] += wx * in2;
+        }
+    }
+}
+
+// K_{i, vertex} contributions of triangle tj for its three stored corners:
+// val[slot] for the vertex in slot 0, 1, 2 of tj.
+__device__ void dlp_triple(const GeoDev &g, int i, int tj, const QuadDev &Q, double val[3])
+{
+    int vi[3] = {g.t0[i], g.t1[i], g.t2[i]};
+    int vj[3] = {g.t0[tj], g.t1[tj], g.t2[tj]};
+    int oi[3], oj[3];
+    int ns = pair_slots(vi, vj, oi, oj);
+    Tri X, Y;
+    load_tri(g, vi[oi[0]], vi[oi[1]], vi[oi[2]], X);
+    load_tri(g, vj[oj[0]], vj[oj[1]], vj[oj[2]], Y);
+    double ny[3] = {g.nx[tj], g.ny[tj], g.nz[tj]};
+    double jj = tri_jac(X) * tri_jac(Y) * INV_4PI;
+    double c3[3];
+    if (ns == 0)
+        pair_regular_dlp3(X, Y, ny, Q, c3);
+    else
+        dlp_touching3(ns, X, Y, ny, Q, c3);
+    // quadrature corner c holds stored slot oj[c]
+    for (int c = 0; c < 3; ++c) val[oj[c]] = c3[c] * jj;
+}
+
 // Column position of panel column c: walk the group's segments.
 __device__ inline int panel_column(const RowPanelDev &d, int g, int c)
 {
@@ -290,6 +376,63 @@ __global__ __launch_bounds__(NT) void k_near_assemble(RowPanelDev d, const int32
             }
         }
         vals[off + e] = v;
+    }
+}
+
+// Double-layer nearfield with every triangle pair integrated once: for each
+// row i of the group, the pair integrals (i, tau) for all triangles tau around
+// the group's column vertices (the sorted list lst[lptr[g] ..]) are computed
+// with all three corner weights into LDS, CH triangles at a time; then every
+// entry (i, j) sums the contributions of the triangles around vertex j in the
+// vertex's own order.
+constexpr int DLP_CH = 1536;
+
+__global__ __launch_bounds__(NT) void k_near_assemble_dlp(RowPanelDev d, const int32_t *__restrict__ rperm,
+                                                          const int32_t *__restrict__ cperm, GeoDev geo, QuadDev Q,
+                                                          const int64_t *__restrict__ lptr,
+                                                          const int32_t *__restrict__ lst, double *__restrict__ vals)
+{
+    __shared__ int32_t tri[DLP_CH];
+    __shared__ double w[3 * DLP_CH];
+    const int g = blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    const int ob = d.out_begin[g];
+    const int64_t off = d.val_off[g];
+    const int64_t l0 = lptr[g];
+    const int nl = (int)(lptr[g + 1] - l0);
+    for (int r = 0; r < nr; ++r) {
+        const int i = rperm[ob + r];
+        for (int h0 = 0; h0 < nl; h0 += DLP_CH) {
+            const int hl = min(DLP_CH, nl - h0);
+            __syncthreads();  // the previous chunk has been read
+            for (int e = threadIdx.x; e < hl; e += NT) {
+                const int tj = lst[l0 + h0 + e];
+                tri[e] = tj;
+                dlp_triple(geo, i, tj, Q, w + 3 * e);
+            }
+            __syncthreads();
+            for (int c = threadIdx.x; c < nc; c += NT) {
+                const int j = cperm[panel_column(d, g, c)];
+                double v = 0.0;
+                for (int64_t a = geo.vt_ptr[j]; a < geo.vt_ptr[j + 1]; ++a) {
+                    const int tj = geo.vt_idx[a];
+                    int lo = 0, hi = hl;  // first position with tri[pos] >= tj
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (tri[mid] < tj)
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (lo < hl && tri[lo] == tj) {
+                        const int slot = (geo.t0[tj] == j) ? 0 : (geo.t1[tj] == j) ? 1 : 2;
+                        v += w[3 * lo + slot];
+                    }
+                }
+                double *dst = vals + off + (int64_t)r * nc + c;
+                *dst = h0 == 0 ? v : *dst + v;
+            }
+        }
     }
 }
 
@@ -885,6 +1028,16 @@ void launch_near_assemble(h2b_kernel kernel, const RowPanels &rp, const int32_t 
         hipLaunchKernelGGL(k_near_assemble<1>, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, rperm,
                            cperm, geo, quad, vals);
     hip_check(hipGetLastError(), "nearfield assembly launch");
+}
+
+void launch_near_assemble_dlp(const RowPanels &rp, const int64_t *lptr, const int32_t *lst, const int32_t *rperm,
+                              const int32_t *cperm, const GeoDev &geo, const QuadDev &quad, double *vals,
+                              hipStream_t st)
+{
+    if (rp.ngroups() == 0) return;
+    hipLaunchKernelGGL(k_near_assemble_dlp, dim3(rp.ngroups()), dim3(NT), 0, st, rp.dev, rperm, cperm, geo, quad,
+                       lptr, lst, vals);
+    hip_check(hipGetLastError(), "double-layer nearfield assembly launch");
 }
 
 void launch_near_grad(const RowPanels &rp, const int32_t *perm, const GeoDev &geo, const QuadDev &quad,

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "device.hpp"
+#include "linalg.hpp"
 #include "op.hpp"
 
 namespace h2b {
@@ -148,6 +149,7 @@ void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t 
     forward_panels(B.trans, B.trans_F);
     B.leaf_F.upload(st);
     B.trans_F.upload(st);
+    build_level_descriptors(B, st);
 }
 
 void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st)
@@ -178,6 +180,48 @@ static void assemble_basis(Basis &B, int m, const DevMem &axes, const GeoDev &ge
 }
 
 // ---------------------------------------------------------- operator
+
+// Nearfield entries of G, or of K with every triangle pair integrated once
+// per row: the sorted triangles around each group's column vertices go to
+// the device for the assembly and are freed afterwards.
+static void assemble_near(Op &op, const QuadDev &Qn, hipStream_t st)
+{
+    if (op.kernel == H2B_SLP) {
+        launch_near_assemble(H2B_SLP, op.near, op.rowb->perm_dev, op.colb->perm_dev, op.geo, Qn,
+                             op.near_vals.as<double>(), st);
+        return;
+    }
+    const Tree &C = *op.colb->tree;
+    const Mesh &M = *C.mesh;
+    const RowPanels &N = op.near;
+    const int ng = N.ngroups();
+    std::vector<std::vector<int32_t>> per(ng);
+    parallel_for(ng, [&](int64_t g) {
+        std::vector<int32_t> &v = per[g];
+        for (int s = N.seg_ptr[g]; s < N.seg_ptr[g + 1]; ++s)
+            for (int p = N.seg_in[s]; p < N.seg_in[s] + N.seg_len[s]; ++p) {
+                const int j = C.perm[p];
+                for (int64_t a = M.vt_ptr[j]; a < M.vt_ptr[j + 1]; ++a) v.push_back(M.vt_idx[a]);
+            }
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    });
+    std::vector<int64_t> lptr(ng + 1, 0);
+    for (int g = 0; g < ng; ++g) lptr[g + 1] = lptr[g] + (int64_t)per[g].size();
+    std::vector<int32_t> lst(std::max<int64_t>(lptr[ng], 1));
+    parallel_for(ng, [&](int64_t g) { std::copy(per[g].begin(), per[g].end(), lst.begin() + lptr[g]); });
+    per.clear();
+    DevMem dptr, dlst;
+    dptr.alloc(sizeof(int64_t) * lptr.size());
+    dlst.alloc(sizeof(int32_t) * lst.size());
+    hip_check(hipMemcpyAsync(dptr.p, lptr.data(), sizeof(int64_t) * lptr.size(), hipMemcpyHostToDevice, st),
+              "triangle list upload");
+    hip_check(hipMemcpyAsync(dlst.p, lst.data(), sizeof(int32_t) * lst.size(), hipMemcpyHostToDevice, st),
+              "triangle list upload");
+    launch_near_assemble_dlp(N, dptr.as<int64_t>(), dlst.as<int32_t>(), op.rowb->perm_dev, op.colb->perm_dev,
+                             op.geo, Qn, op.near_vals.as<double>(), st);
+    hip_check(hipStreamSynchronize(st), "double-layer nearfield assembly");
+}
 
 Op::~Op()
 {
@@ -335,8 +379,7 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     // values
     op->near_vals.alloc(sizeof(double) * std::max<int64_t>(op->near.total, 1));
     QuadDev Qn = make_quad(p.q_near);
-    launch_near_assemble(kernel, op->near, op->rowb->perm_dev, op->colb->perm_dev, op->geo, Qn,
-                         op->near_vals.as<double>(), st);
+    assemble_near(*op, Qn, st);
     // with recompression the interpolation operator is built in FP64 first
     const bool rc = p.recompress_tol > 0.0;
     const h2b_dtype adt = rc ? H2B_F64 : p.farfield_dtype;
@@ -428,6 +471,10 @@ void make_transposed_copies(Op &op, hipStream_t st)
 template <typename F>
 static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
 {
+    if (B.lev) {
+        forward_levels<F>(B, xp, xhat, st);
+        return;
+    }
     launch_colpanel<F, double, F>(B.leaf_F, 0, B.leaf_F.ngroups(), B.leafT_vals.as<F>(), xp, xhat, st,
                                   Role::Leaf, false);
     for (auto &s : B.fw_steps)
@@ -438,6 +485,10 @@ static void forward(const Basis &B, const double *xp, F *xhat, hipStream_t st)
 template <typename F>
 static void backward(const Basis &B, F *yhat, double *yp, hipStream_t st)
 {
+    if (B.lev) {
+        backward_levels<F>(B, yhat, yp, st);
+        return;
+    }
     for (auto it = B.fw_steps.rbegin(); it != B.fw_steps.rend(); ++it)
         launch_rowpanelT<F, F, F>(B.trans, it->first, it->second, B.trans_vals.as<F>(), yhat, yhat, st,
                                   Role::Transfer);
@@ -519,14 +570,16 @@ static void product_piece(Op &op, const Work &w, int trans, double alpha, const 
     };
     switch (pc) {
     case Piece::Prepare:
+        // the nearfield's output is cleared here too: on its own stream the
+        // fill would wait behind the forward transformation's workgroups
         launch_fill_zero<F>(yhat, Bout.hat_total, st);
         launch_fill_zero<double>(yp, nout, st);
+        launch_fill_zero<double>(ypn, nout, st);
         mark(0);
         launch_gather(Bin.perm_dev, nin, 1, x, nin, xp, st);
         mark(1);
         break;
     case Piece::Near:
-        launch_fill_zero<double>(ypn, nout, st);
         mark(5);
         if (op.sym && w.sym)
             symmetric_near_product(op, trans, xp, ypn, st);
@@ -701,12 +754,12 @@ static void product_block(Op &op, const Work &w, int trans, double alpha, const 
     };
     launch_fill_zero<F>(yhat, Bout.hat_total * rb, st);
     launch_fill_zero<double>(yp, nout * rb, st);
+    launch_fill_zero<double>(ypn, nout * rb, st);
     mark(0, st);
     launch_gather_mrhs(Bin.perm_dev, nin, nb, rb, x, ldx, xp, st);
     mark(1, st);
     hipStream_t ns = fork_side(op, st);
     auto nearfield = [&] {
-        launch_fill_zero<double>(ypn, nout * rb, ns);
         mark(5, ns);
         const RowPanels &NP = trans ? op.near_R : op.near;
         const double *nv = trans ? op.near_R_vals.as<double>() : op.near_vals.as<double>();
@@ -1056,8 +1109,7 @@ void set_geometry(Op &op, const double *vx, const double *vy, const double *vz, 
     up(nz.data(), op.geo.nz, nt);
     hip_check(hipStreamSynchronize(st), "geometry upload");
     QuadDev Qn = make_quad(op.params.q_near);
-    launch_near_assemble(op.kernel, op.near, op.rowb->perm_dev, op.colb->perm_dev, op.geo, Qn,
-                         op.near_vals.as<double>(), st);
+    assemble_near(op, Qn, st);
     std::vector<Basis *> bases{op.rowb.get()};
     if (op.colb != op.rowb) bases.push_back(op.colb.get());
     const int m = op.params.order_m;

@@ -12,6 +12,15 @@
 
 namespace h2b {
 
+// Work descriptors of the single-vector basis transformations (transform.hip):
+// one per cluster with coefficients, the leaves first, then the parents by
+// level from the deepest; step[k] .. step[k + 1] is one launch.
+struct LevelDescs {
+    std::vector<int32_t> desc, step;
+    const int32_t *d_desc = nullptr;
+    DevMem mem;
+};
+
 // Cluster basis on one tree: leaf matrices (stored transposed) and transfer
 // matrices, each with the panel descriptors of the forward (rows) and the
 // backward (transposed) products.
@@ -41,6 +50,7 @@ struct Basis {
     ColPanels proj_T;
     DevMem proj_vals;
     bool has_proj = false;
+    std::unique_ptr<LevelDescs> lev;        // descriptors of the single-vector transformations
 };
 
 // Nearfield of G on one cluster tree stored once per pair of leaves: for every
@@ -131,17 +141,6 @@ inline size_t coupling_size(h2b_dtype dt)
 
 QuadDev make_quad(int q);
 
-// Green cross approximation on one tree (triangles, or the vertices of K's
-// columns): per cluster the rank k_t, the pivots t_hat (original indices,
-// pivot order) and V, the leaf basis
-// (|t| x k_t, position order) or the stacked transfers [E_1; E_2]
-// ((k_1 + k_2) x k_t), both row-major.
-struct GcaBases {
-    std::vector<int> rank;
-    std::vector<std::vector<int32_t>> hat;
-    std::vector<std::vector<double>> V;
-};
-GcaBases gca_bases(const Tree &T, int m, double eps);
 // Basis values (in the far-field dtype) and coupling entries A|_{t_hat x s_hat}
 // of an operator whose panels were built with the GCA ranks (Gr: row tree,
 // Gc: column tree, the same object for G).
@@ -150,6 +149,10 @@ void set_gca_values(Op &op, const GcaBases &Gr, const GcaBases &Gc, hipStream_t 
 std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel kernel,
                                 const h2b_params &p, hipStream_t st);
 void build_basis_structure(Basis &B, const std::vector<int> &ranks, hipStream_t st);
+// Subtree schedule of a basis (from its final panels).
+void build_level_descriptors(Basis &B, hipStream_t st);
+template <typename F> void forward_levels(const Basis &B, const double *xp, F *xhat, hipStream_t st);
+template <typename F> void backward_levels(const Basis &B, F *yhat, double *yp, hipStream_t st);
 // Transposed copies of the leaf and transfer values (after they are final).
 void transpose_basis_values(Basis &B, h2b_dtype dt, hipStream_t st);
 void recompress_op(Op &op, double tol, hipStream_t st);

@@ -421,8 +421,11 @@ def test_tuner_picks_a_tile_and_products_stay_exact():
 def test_batched_graph_of_uneven_meshes():
     """Sixteen meshes of uneven size (spheres of random radius and ellipsoids
     with random semi-axes, 2 s^2 ... triangles) captured into one graph: every
-    replay equals the eager products, with eager work and synchronisations
-    between replays."""
+    replay is bitwise the first one, with eager work and synchronisations
+    between replays, and equals the eager products up to FP32 rounding.  The
+    far field is FP32 and the merged launches sum the transformations in
+    another order than the per-level launches of one product: a few FP32 ulps
+    (2^-24 = 6e-8) of the largest entry, bounded here by 1e-6 of it."""
     torch = _torch()
     h = _lib()
     rng = np.random.default_rng(302)
@@ -448,15 +451,19 @@ def test_batched_graph_of_uneven_meshes():
         refs.append(ref)
     torch.cuda.synchronize()
     batch = h.Batch(list(zip(ops, xs, ys)))
+    first = None
     for rep in range(4):
         for y in ys:
             y.zero_()
         torch.cuda.synchronize()
         batch.launch()
         torch.cuda.synchronize()
-        for y, ref in zip(ys, refs):
-            np.testing.assert_allclose(y.cpu().numpy(), ref.cpu().numpy(), rtol=0,
-                                       atol=1e-12 * float(ref.abs().max()))
+        got = [y.cpu().numpy() for y in ys]
+        if first is None:
+            first = got
+        for g, f, ref in zip(got, first, refs):
+            np.testing.assert_array_equal(g, f)
+            np.testing.assert_allclose(g, ref.cpu().numpy(), rtol=0, atol=1e-6 * float(ref.abs().max()))
         # eager work in between replays
         ops[0].matvec(xs[0], refs[0], alpha=0.0)
         torch.cuda.synchronize()
