@@ -469,16 +469,95 @@ h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, dou
  * leaves of at most 64; product form only).  The inverses are computed on
  * the device by the first such solve (sum of |t|^2 doubles, kept by the
  * operator); applying P reads them once per iteration.  The stopping test
- * and the residuals stay on ||r||.  This is not the paper's H-Cholesky
- * preconditioner.
+ * and the residuals stay on ||r||.  This is a simpler stand-in for the
+ * paper's preconditioner.  precond = H2B_PRECOND_HCHOL runs preconditioned CG
+ * with z = (L L^T)^{-1} r from the factor params.hchol (see
+ * h2b_hchol_build; the paper's preconditioner), whose size must be n; product
+ * form only.
  *
  * Errors: H2B_EINVAL for a non-square operator (not the single-layer
  * operator for the hypersingular form), an unknown form or preconditioner,
  * NULL or overlapping b and x, tol < 0 or not finite, max_iter < 0,
- * check_every < 1; H2B_ENOTSUP for the block-Jacobi preconditioner on other
- * operators, larger leaves or the hypersingular form. */
+ * check_every < 1, H2B_PRECOND_HCHOL with a NULL factor or one of another
+ * size; H2B_ENOTSUP for the block-Jacobi preconditioner on other operators,
+ * larger leaves, and for either preconditioner with the hypersingular
+ * form. */
 typedef enum { H2B_FORM_PRODUCT = 0, H2B_FORM_HYPERSINGULAR = 1 } h2b_cg_form;
-typedef enum { H2B_PRECOND_NONE = 0, H2B_PRECOND_BLOCK_JACOBI = 1 } h2b_cg_precond;
+typedef enum { H2B_PRECOND_NONE = 0, H2B_PRECOND_BLOCK_JACOBI = 1, H2B_PRECOND_HCHOL = 2 } h2b_cg_precond;
+
+/* ---------------------------------------------- H-Cholesky preconditioner
+ *
+ * The paper preconditions its conjugate gradient solves by coarsening the
+ * compressed matrix to a relative accuracy eps_prc and factorising it,
+ * G ~ L L^T, in H-matrix arithmetic (Section 1; the eps_prc column of the
+ * parameter table of Section 5).  Here:
+ *  - the lower triangle of G becomes an H-matrix on its cluster and block
+ *    trees: a farfield block V_t S_ts V_s^T the low-rank product U V^T with
+ *    U = V_t S_ts and V = V_s (the parent bases made explicit through the
+ *    transfer matrices of Section 2, eq. (transfer)), a nearfield block a
+ *    dense array;
+ *  - coarsening: every low-rank block is truncated to the singular values
+ *    above eps times its largest, every off-diagonal dense block made
+ *    low-rank where that stores fewer values, and, from the leaves up, every
+ *    off-diagonal subdivided block whose parts are all leaves replaced by one
+ *    truncated low-rank block where that stores fewer values;
+ *  - H-Cholesky: L11 = chol(G11), L21 = G21 L11^{-T}, L22 = chol(G22 - L21 L21^T)
+ *    recursively over the diagonal blocks, every product of blocks formed in
+ *    low-rank or dense arithmetic and every low-rank result truncated to eps.
+ * Setup runs on the host (the values of G are copied from the device once).
+ * Applying z = (L L^T)^{-1} r runs on the device: forward and backward
+ * substitution over the block recursion, flattened into a list of steps of
+ * independent tasks (the inverse of a dense diagonal factor, the
+ * coefficients V^T y of the low-rank blocks of an update, the rows of a leaf
+ * cluster changed by an update) run by one workgroup, since the chain of
+ * diagonal leaves is sequential. */
+typedef struct h2b_hchol_s *h2b_hchol;
+
+typedef struct {
+    int64_t n;                      /* rows */
+    double eps;                     /* truncation accuracy */
+    int64_t coarse_entries;         /* stored doubles after coarsening */
+    int64_t dense_entries;          /* stored doubles of the factor in dense blocks */
+    int64_t rk_entries;             /* ... and in low-rank blocks */
+    int64_t dense_blocks, rk_blocks;
+    int max_rank;                   /* largest rank of a block of the factor */
+    int64_t coarsened_blocks;       /* subdivided blocks replaced by one low-rank block */
+    int64_t converted_blocks;       /* dense blocks replaced by low-rank ones */
+    int64_t steps, tasks;           /* substitution program: steps and tasks of both sweeps (0 before
+                                       the first device use) */
+    double convert_s, coarsen_s, factor_s, upload_s;  /* host wall time of the setup stages */
+} h2b_hchol_info;
+
+/* Builds the preconditioner of the single-layer operator G (FP64 far field,
+ * stored couplings, one cluster tree for rows and columns) to accuracy
+ * eps >= 0 (0: exact up to rounding, dense storage) and uploads its
+ * substitution program.  Synchronises hip_stream.  Errors: H2B_EINVAL for a
+ * NULL or non-single-layer G, eps < 0 or not finite; H2B_ENOTSUP for other
+ * far-field settings, dense diagonal leaves above 256 rows, or a pivot that
+ * is not positive (the coarsened matrix is not positive definite at this eps:
+ * use a smaller one). */
+h2b_status h2b_hchol_build(h2b_op G, double eps, h2b_hchol *out, void *hip_stream);
+
+/* The same from a dense symmetric matrix A (n x n, row-major, host memory,
+ * the caller's numbering of the blocks' tree; n = tree size) on the blocks of
+ * one P0 tree: nearfield leaves copied, farfield leaves truncated to eps by
+ * a singular value decomposition.  Host only (no device use until
+ * h2b_hchol_apply).  Errors: H2B_EINVAL for NULL arguments, blocks on two
+ * trees, eps < 0; H2B_ENOTSUP as above. */
+h2b_status h2b_hchol_from_dense(h2b_blocks blocks, const double *A, double eps, h2b_hchol *out);
+
+/* z = (L L^T)^{-1} r on the host (r, z: host arrays of n doubles, caller's
+ * numbering; may be the same array). */
+h2b_status h2b_hchol_solve_host(h2b_hchol P, const double *r, double *z);
+
+/* z = (L L^T)^{-1} r on the device (r, z: device arrays of n doubles, caller's
+ * numbering, not overlapping), asynchronous on hip_stream.  The first call
+ * uploads the program if the handle came from h2b_hchol_from_dense.  Uses
+ * the handle's work vectors: calls on one handle must not overlap. */
+h2b_status h2b_hchol_apply(h2b_hchol P, const double *r, double *z, void *hip_stream);
+
+h2b_status h2b_hchol_get_info(h2b_hchol P, h2b_hchol_info *info);
+h2b_status h2b_hchol_destroy(h2b_hchol P);
 
 typedef struct {
     double tol;        /* relative residual to reach (default 1e-8) */
@@ -487,7 +566,8 @@ typedef struct {
     int use_graph;     /* 1: replay a HIP graph of check_every iterations (default 1) */
     int zero_guess;    /* 1: start from x = 0 without the initial product (default 1) */
     int form;          /* h2b_cg_form: the operator's product (default) or W built from G */
-    int precond;       /* h2b_cg_precond: none (default) or block Jacobi, see below */
+    int precond;       /* h2b_cg_precond: none (default), block Jacobi or H-Cholesky, see below */
+    h2b_hchol hchol;   /* the factor for H2B_PRECOND_HCHOL (NULL otherwise; default NULL) */
 } h2b_cg_params;
 
 typedef enum { H2B_CG_CONVERGED = 1, H2B_CG_BREAKDOWN = 2, H2B_CG_MAXITER = 3 } h2b_cg_status;

@@ -59,7 +59,15 @@ class h2b_op_stats(ctypes.Structure):
 class h2b_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int), ("form", ctypes.c_int),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("hchol", _vp)]
+
+
+class h2b_hchol_info(ctypes.Structure):
+    _fields_ = [("n", _i64), ("eps", ctypes.c_double), ("coarse_entries", _i64), ("dense_entries", _i64),
+                ("rk_entries", _i64), ("dense_blocks", _i64), ("rk_blocks", _i64), ("max_rank", ctypes.c_int),
+                ("coarsened_blocks", _i64), ("converted_blocks", _i64), ("steps", _i64), ("tasks", _i64),
+                ("convert_s", ctypes.c_double), ("coarsen_s", ctypes.c_double), ("factor_s", ctypes.c_double),
+                ("upload_s", ctypes.c_double)]
 
 
 class h2b_cg_result(ctypes.Structure):
@@ -70,8 +78,9 @@ class h2b_cg_result(ctypes.Structure):
 H2B_CG_CONVERGED, H2B_CG_BREAKDOWN, H2B_CG_MAXITER = 1, 2, 3
 H2B_FORM_PRODUCT, H2B_FORM_HYPERSINGULAR = 0, 1
 _FORMS = {"product": H2B_FORM_PRODUCT, "hypersingular": H2B_FORM_HYPERSINGULAR}
-H2B_PRECOND_NONE, H2B_PRECOND_BLOCK_JACOBI = 0, 1
-_PRECONDS = {None: H2B_PRECOND_NONE, "none": H2B_PRECOND_NONE, "block_jacobi": H2B_PRECOND_BLOCK_JACOBI}
+H2B_PRECOND_NONE, H2B_PRECOND_BLOCK_JACOBI, H2B_PRECOND_HCHOL = 0, 1, 2
+_PRECONDS = {None: H2B_PRECOND_NONE, "none": H2B_PRECOND_NONE, "block_jacobi": H2B_PRECOND_BLOCK_JACOBI,
+             "hchol": H2B_PRECOND_HCHOL}
 CG_STATUS = {H2B_CG_CONVERGED: "converged", H2B_CG_BREAKDOWN: "breakdown", H2B_CG_MAXITER: "max_iter"}
 
 
@@ -109,6 +118,12 @@ _SIGS = {
     "h2b_cg_params_default": ([_P(h2b_cg_params)], None),
     "h2b_cg_solve": ([_vp, _vp, _vp, _P(h2b_cg_params), _P(h2b_cg_result), _vp, _vp], ctypes.c_int),
     "h2b_hypersingular_matvec": ([_vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_hchol_build": ([_vp, _dbl, _P(_vp), _vp], ctypes.c_int),
+    "h2b_hchol_from_dense": ([_vp, _vp, _dbl, _P(_vp)], ctypes.c_int),
+    "h2b_hchol_solve_host": ([_vp, _vp, _vp], ctypes.c_int),
+    "h2b_hchol_apply": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "h2b_hchol_get_info": ([_vp, _P(h2b_hchol_info)], ctypes.c_int),
+    "h2b_hchol_destroy": ([_vp], ctypes.c_int),
 }
 
 _ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
@@ -204,8 +219,8 @@ class Mesh:
         self.handle = h
         self.nv, self.nt = len(v), len(t)
 
-    def __del__(self, _destroy=h2b_mesh_destroy):
-        if getattr(self, "handle", None) and not _EXITING[0]:
+    def __del__(self, _destroy=h2b_mesh_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -239,8 +254,8 @@ class Tree:
         offs = np.concatenate([[0], np.cumsum(ranks)])
         return ranks, [piv[offs[c]:offs[c + 1]] for c in range(self.nclusters)]
 
-    def __del__(self, _destroy=h2b_tree_destroy):
-        if getattr(self, "handle", None) and not _EXITING[0]:
+    def __del__(self, _destroy=h2b_tree_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -261,8 +276,8 @@ class Blocks:
         _check(h2b_blocks_lists(self.handle, _ptr(far), _ptr(near)))
         return far, near
 
-    def __del__(self, _destroy=h2b_blocks_destroy):
-        if getattr(self, "handle", None) and not _EXITING[0]:
+    def __del__(self, _destroy=h2b_blocks_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -389,12 +404,13 @@ class Operator:
         return y
 
     def cg(self, b, x, tol=1e-8, max_iter=1000, check_every=8, use_graph=True, zero_guess=True,
-           history=False, form="product", precond=None, stream=None):
+           history=False, form="product", precond=None, hchol=None, stream=None):
         """Conjugate gradients for A x = b (A square, symmetric positive
         definite: the single-layer matrix G), or with form="hypersingular"
         for W x = b, W built from this single-layer operator; precond=
         "block_jacobi" preconditions with the inverse diagonal nearfield
-        blocks of the leaves.  x holds the
+        blocks of the leaves, precond="hchol" with the H-Cholesky factor
+        `hchol` (an HChol of this operator).  x holds the
         initial guess (unless zero_guess) and receives the solution.  Returns
         a dict with iterations, status, rel_residual, solve_ms and, with
         history, the relative residual norms of iterations 0..iterations."""
@@ -414,6 +430,10 @@ class Operator:
         p.use_graph, p.zero_guess = int(bool(use_graph)), int(bool(zero_guess))
         p.form = _FORMS[form]
         p.precond = _PRECONDS[precond]
+        if precond == "hchol":
+            if not isinstance(hchol, HChol):
+                raise ValueError('precond="hchol" needs hchol=HChol(...)')
+            p.hchol = hchol.handle
         r = h2b_cg_result()
         hist = np.zeros(max(int(max_iter), 0) + 1) if history else None
         _check(h2b_cg_solve(self.handle, _vp(b.data_ptr()), _vp(x.data_ptr()), ctypes.byref(p), ctypes.byref(r),
@@ -424,8 +444,56 @@ class Operator:
             out["history"] = hist[:r.iterations + 1]
         return out
 
-    def __del__(self, _destroy=h2b_op_destroy):
-        if getattr(self, "handle", None) and not _EXITING[0]:
+    def __del__(self, _destroy=h2b_op_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
+            _destroy(self.handle)
+            self.handle = None
+
+
+class HChol:
+    """H-Cholesky preconditioner G ~ L L^T of a single-layer operator,
+    coarsened and factorised to the blockwise accuracy eps on the host; its
+    substitutions z = (L L^T)^{-1} r run on the device (apply) or on the host
+    (solve_host).  HChol(op, eps) builds it from an Operator;
+    HChol.from_dense(blocks, A, eps) from a dense symmetric matrix on the
+    blocks of one triangle tree (host only until the first apply)."""
+
+    def __init__(self, op=None, eps=1e-3, stream=None, _handle=None, _keep=None):
+        self.handle = None
+        if _handle is not None:
+            self.handle, self._keep = _handle, _keep
+            return
+        h = _vp()
+        _check(h2b_hchol_build(op.handle, float(eps), ctypes.byref(h), _stream_ptr(stream)))
+        self.handle, self._keep = h, op
+
+    @classmethod
+    def from_dense(cls, blocks, A, eps):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        h = _vp()
+        _check(h2b_hchol_from_dense(blocks.handle, _ptr(A), float(eps), ctypes.byref(h)))
+        return cls(_handle=h, _keep=blocks)
+
+    def info(self):
+        s = h2b_hchol_info()
+        _check(h2b_hchol_get_info(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def solve_host(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.empty_like(r)
+        _check(h2b_hchol_solve_host(self.handle, _ptr(r), _ptr(z)))
+        return z
+
+    def apply(self, r, z, stream=None):
+        n = self.info()["n"]
+        _vector(r, n, "r")
+        _vector(z, n, "z")
+        _check(h2b_hchol_apply(self.handle, _vp(r.data_ptr()), _vp(z.data_ptr()), _stream_ptr(stream)))
+        return z
+
+    def __del__(self, _destroy=h2b_hchol_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
 
@@ -489,8 +557,8 @@ class Batch:
     def launch(self, stream=None):
         _check(h2b_batch_launch(self.handle, _stream_ptr(stream)))
 
-    def __del__(self, _destroy=h2b_batch_destroy):
-        if getattr(self, "handle", None) and not _EXITING[0]:
+    def __del__(self, _destroy=h2b_batch_destroy, _exiting=_EXITING):
+        if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
 

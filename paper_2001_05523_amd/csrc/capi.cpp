@@ -7,6 +7,7 @@
 #include <mutex>
 #include <string>
 
+#include "hchol.hpp"
 #include "op.hpp"
 
 struct h2b_mesh_s {
@@ -404,6 +405,122 @@ void h2b_cg_params_default(h2b_cg_params *p)
     p->zero_guess = 1;
     p->form = H2B_FORM_PRODUCT;
     p->precond = H2B_PRECOND_NONE;
+    p->hchol = nullptr;
+}
+
+h2b_status h2b_hchol_build(h2b_op G, double eps, h2b_hchol *out, void *hip_stream)
+{
+    return guarded([&] {
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        h2b::AllocStreamScope scope(st);
+        need(G, "G");
+        need(out, "out");
+        if (!(eps >= 0.0) || !std::isfinite(eps)) h2b::fail(H2B_EINVAL, "eps must be finite and >= 0");
+        auto P = std::make_unique<h2b::HChol>();
+        P->eps = eps;
+        auto t0 = std::chrono::steady_clock::now();
+        P->H = h2b::hmatrix_from_op(*G->op, eps, st);
+        P->convert_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        h2b::hchol_factor(*P, eps);
+        t0 = std::chrono::steady_clock::now();
+        h2b::hchol_upload(*P, st);
+        P->upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = new h2b_hchol_s{std::move(P)};
+    });
+}
+
+h2b_status h2b_hchol_from_dense(h2b_blocks blocks, const double *A, double eps, h2b_hchol *out)
+{
+    return guarded([&] {
+        need(blocks, "blocks");
+        need(A, "A");
+        need(out, "out");
+        if (!(eps >= 0.0) || !std::isfinite(eps)) h2b::fail(H2B_EINVAL, "eps must be finite and >= 0");
+        const h2b::Blocks &B = *blocks->b;
+        if (B.rows != B.cols) h2b::fail(H2B_EINVAL, "the blocks must be on one cluster tree");
+        const h2b::Tree &T = *B.rows;
+        const int64_t n = T.n;
+        std::vector<double> Ap((size_t)n * n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) Ap[(size_t)i * n + j] = A[(size_t)T.perm[i] * n + T.perm[j]];
+        auto P = std::make_unique<h2b::HChol>();
+        P->eps = eps;
+        auto t0 = std::chrono::steady_clock::now();
+        P->H = h2b::hmatrix_from_dense(B, Ap.data(), eps);
+        P->convert_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        h2b::hchol_factor(*P, eps);
+        *out = new h2b_hchol_s{std::move(P)};
+    });
+}
+
+h2b_status h2b_hchol_solve_host(h2b_hchol P, const double *r, double *z)
+{
+    return guarded([&] {
+        need(P, "P");
+        need(r, "r");
+        need(z, "z");
+        const h2b::Tree &T = *P->p->H->tree;
+        std::vector<double> x((size_t)T.n);
+        for (int64_t i = 0; i < T.n; ++i) x[i] = r[T.perm[i]];
+        h2b::hchol_flatten(*P->p);
+        h2b::hprogram_run(P->p->prog_host, T.n, x.data());
+        for (int64_t i = 0; i < T.n; ++i) z[T.perm[i]] = x[i];
+    });
+}
+
+h2b_status h2b_hchol_apply(h2b_hchol P, const double *r, double *z, void *hip_stream)
+{
+    return guarded([&] {
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        h2b::AllocStreamScope scope(st);
+        need(P, "P");
+        need(r, "r");
+        need(z, "z");
+        const int64_t n = P->p->H->tree->n;
+        const char *rb = reinterpret_cast<const char *>(r), *zb = reinterpret_cast<const char *>(z);
+        if (rb < zb + sizeof(double) * n && zb < rb + sizeof(double) * n) h2b::fail(H2B_EINVAL, "r and z overlap");
+        if (!P->p->uploaded) {
+            const auto t0 = std::chrono::steady_clock::now();
+            h2b::hchol_upload(*P->p, st);
+            P->p->upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        h2b::hchol_apply(*P->p, r, z, st);
+    });
+}
+
+h2b_status h2b_hchol_get_info(h2b_hchol P, h2b_hchol_info *info)
+{
+    return guarded([&] {
+        need(P, "P");
+        need(info, "info");
+        const h2b::HChol &H = *P->p;
+        h2b_hchol_info o{};
+        o.n = H.H->tree->n;
+        o.eps = H.eps;
+        o.coarse_entries = H.coarse.dense_entries + H.coarse.rk_entries;
+        o.dense_entries = H.factor.dense_entries;
+        o.rk_entries = H.factor.rk_entries;
+        o.dense_blocks = H.factor.dense_blocks;
+        o.rk_blocks = H.factor.rk_blocks;
+        o.max_rank = H.factor.max_rank;
+        o.coarsened_blocks = H.factor.coarsened;
+        o.converted_blocks = H.factor.converted;
+        o.steps = H.nsteps;
+        o.tasks = H.ntasks;
+        o.convert_s = H.convert_s;
+        o.coarsen_s = H.coarsen_s;
+        o.factor_s = H.factor_s;
+        o.upload_s = H.upload_s;
+        *info = o;
+    });
+}
+
+h2b_status h2b_hchol_destroy(h2b_hchol P)
+{
+    return guarded([&] {
+        if (P && P->p && P->p->uploaded) (void)hipDeviceSynchronize();
+        delete P;
+    });
 }
 
 h2b_status h2b_hypersingular_matvec(h2b_op G, double alpha, const double *x, double *y, void *hip_stream)

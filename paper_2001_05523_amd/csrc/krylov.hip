@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 
+#include "hchol.hpp"
 #include "op.hpp"
 
 namespace h2b {
@@ -523,10 +524,13 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
     const auto t0 = std::chrono::steady_clock::now();
     const bool hyp = prm.form == H2B_FORM_HYPERSINGULAR;
     if (prm.form != H2B_FORM_PRODUCT && !hyp) fail(H2B_EINVAL, "unknown operator form");
-    if (prm.precond != H2B_PRECOND_NONE && prm.precond != H2B_PRECOND_BLOCK_JACOBI)
+    if (prm.precond != H2B_PRECOND_NONE && prm.precond != H2B_PRECOND_BLOCK_JACOBI &&
+        prm.precond != H2B_PRECOND_HCHOL)
         fail(H2B_EINVAL, "unknown preconditioner");
-    const bool pc = prm.precond == H2B_PRECOND_BLOCK_JACOBI;
-    if (pc && hyp) fail(H2B_ENOTSUP, "the block-Jacobi preconditioner is built for the product form");
+    const bool hc = prm.precond == H2B_PRECOND_HCHOL;
+    const bool pc = prm.precond != H2B_PRECOND_NONE;
+    if (pc && hyp) fail(H2B_ENOTSUP, "the preconditioners are built for the product form");
+    if (hc && (!prm.hchol || !prm.hchol->p)) fail(H2B_EINVAL, "H2B_PRECOND_HCHOL needs the factor (params.hchol)");
     if (hyp) check_single_layer(A);
     if (!hyp && A.nrows != A.ncols) fail(H2B_EINVAL, "conjugate gradients need a square operator");
     const int64_t n = hyp ? A.blocks->rows->mesh->nv : A.nrows;
@@ -546,7 +550,12 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         prepare_hypersingular(A);
     else
         prepare_product(A, 1);
-    if (pc) prepare_block_jacobi(A, st);
+    if (hc) {
+        if (prm.hchol->p->H->tree->n != n) fail(H2B_EINVAL, "the H-Cholesky factor has another size");
+        if (!prm.hchol->p->uploaded) hchol_upload(*prm.hchol->p, st);
+    } else if (pc) {
+        prepare_block_jacobi(A, st);
+    }
 
     CgRun w;
     const int nb = grid_for(n);
@@ -564,10 +573,14 @@ void cg_solve(Op &A, const double *b, double *x, const h2b_cg_params &prm, h2b_c
         w.part3.alloc(sizeof(double) * KMAXB);
     }
     double *z = pc ? w.z.as<double>() : nullptr, *part3 = pc ? w.part3.as<double>() : nullptr;
-    // z = P r (block Jacobi) for the leaves of the operator's row tree
+    // z = P r: block Jacobi over the leaves of the operator's row tree, or
+    // the substitutions with the H-Cholesky factor
     auto precondition = [&](hipStream_t s) {
-        hipLaunchKernelGGL(k_bj_apply, dim3(A.bj_leaves), dim3(KT), 0, s, A.bj_begin, A.bj_n, A.bj_dst,
-                           A.rowb->perm_dev, A.bj_inv.as<double>(), w.r.as<double>(), z);
+        if (hc)
+            hchol_apply(*prm.hchol->p, w.r.as<double>(), z, s);
+        else
+            hipLaunchKernelGGL(k_bj_apply, dim3(A.bj_leaves), dim3(KT), 0, s, A.bj_begin, A.bj_n, A.bj_dst,
+                               A.rowb->perm_dev, A.bj_inv.as<double>(), w.r.as<double>(), z);
         hipLaunchKernelGGL(k_dot_part, dim3(grid_for(n)), dim3(KT), 0, s, w.r.as<double>(), z, n, part3);
     };
     double *r = w.r.as<double>(), *p = w.p.as<double>(), *q = w.q.as<double>();

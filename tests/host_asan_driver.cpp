@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "h2b_internal.hpp"
+#include "hmatrix.hpp"
 #include "linalg.hpp"
 
 using namespace h2b;
@@ -157,6 +158,43 @@ void check_gca(const Tree &T, int m, double eps)
     }
 }
 
+// H-matrix coarsening, H-Cholesky and the substitution program on a
+// symmetric positive definite kernel matrix exp(-|c_i - c_j| / 0.3) + 1e-3 I
+// over the triangle centroids: the program's solve equals the recursive one,
+// and eps = 0 solves exactly.
+void check_hchol(const Mesh &M, std::shared_ptr<Tree> T, double eps)
+{
+    const int n = (int)T->n;
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int a = T->perm[i], b = T->perm[j];
+            const double dx = M.cx[a] - M.cx[b], dy = M.cy[a] - M.cy[b], dz = M.cz[a] - M.cz[b];
+            A[(size_t)i * n + j] = std::exp(-std::sqrt(dx * dx + dy * dy + dz * dz) / 0.3) + (i == j ? 1e-3 : 0.0);
+        }
+    auto B = build_blocks(T, T, 1.0, false);
+    auto H = hmatrix_from_dense(*B, A.data(), eps);
+    hmatrix_coarsen(*H, eps);
+    hmatrix_cholesky(*H);
+    HProgram P;
+    hprogram_build(*H, P);
+    std::vector<double> x(n), b(n, 0.0);
+    for (int i = 0; i < n; ++i) x[i] = std::sin(0.37 * i + 1.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) b[i] += A[(size_t)i * n + j] * x[j];
+    std::vector<double> z1 = b, z2 = b;
+    hmatrix_solve(*H, z1.data());
+    hprogram_run(P, n, z2.data());
+    double d = 0, e = 0, nx = 0;
+    for (int i = 0; i < n; ++i) {
+        d = std::fmax(d, std::fabs(z1[i] - z2[i]));
+        e += (z1[i] - x[i]) * (z1[i] - x[i]);
+        nx += x[i] * x[i];
+    }
+    check(d <= 1e-9 * std::sqrt(nx), "program solve equals the recursive solve");
+    if (eps == 0.0) check(std::sqrt(e / nx) <= 1e-8, "exact H-Cholesky solves exactly");
+}
+
 }  // namespace
 
 int main()
@@ -199,6 +237,11 @@ int main()
             }
         }
     }
+    for (int leaf : {5, 16})
+        for (double eps : {0.0, 1e-4, 1e-2}) {
+            auto M = to_mesh(octa_sphere(6));
+            check_hchol(*M, build_tree(M, H2B_P0, leaf), eps);
+        }
     {
         auto M = to_mesh(plate(12));
         auto R = build_tree(M, H2B_P0, 8);

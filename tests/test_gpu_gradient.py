@@ -74,7 +74,7 @@ def test_adjoint_close_to_dense_oracle_gradient():
     rng = np.random.default_rng(405)
     scale = np.abs(g).max()
     errs = []
-    for v in rng.choice(len(verts), 4, replace=False):
+    for v in rng.choice(len(verts), 12, replace=False):
         for d in range(3):
             vp = verts.copy()
             vp[v, d] += 1e-6
@@ -83,7 +83,41 @@ def test_adjoint_close_to_dense_oracle_gradient():
             fm = xn @ oracle.slp_dense(vp, tris, q) @ yn
             errs.append(abs((fp - fm) / 2e-6 - g[v, d]) / scale)
     print("max |adjoint - oracle FD| / max|grad| = %.3e" % max(errs))
-    assert max(errs) <= 5e-3
+    # the H^2 form differs from the dense one by the order-4 interpolation
+    # error of the far field (about 1e-4 of the gradient on this mesh)
+    assert max(errs) <= 5e-4
+
+
+@pytest.mark.parametrize("s,nvert", [(4, None), (8, 16)])
+def test_adjoint_equals_dense_oracle_gradient_without_far_field(s, nvert):
+    """Far field disabled, so x^T G y is the dense Galerkin form of the
+    oracle: the adjoint gradient must equal central differences of the
+    oracle's dense matrix (same quadrature, h = 1e-6) up to the difference
+    error, at every vertex of the 128-triangle sphere and at 16 vertices of
+    the 512-triangle one.  A central difference of a form of size |b| in
+    FP64 carries about eps |b| / h ~ 1e-10 |b| of rounding, plus h^2 terms."""
+    torch = _torch()
+    h2b = _lib()
+    verts, tris = synth.perturbed_sphere(s, 401 + s)
+    q = 4
+    op = h2b.Operator(verts, tris, kernel="slp", leaf=16, q_near=q, far_disabled=True)
+    xn = synth.random_vector(len(tris), 412)
+    yn = synth.random_vector(len(tris), 413)
+    g = op.shape_grad(torch.tensor(xn, device="cuda"), torch.tensor(yn, device="cuda")).cpu().numpy()
+    scale = np.abs(g).max()
+    rng = np.random.default_rng(414)
+    vs = range(len(verts)) if nvert is None else rng.choice(len(verts), nvert, replace=False)
+    err = 0.0
+    for v in vs:
+        for d in range(3):
+            vp = verts.copy()
+            vp[v, d] += 1e-6
+            fp = xn @ oracle.slp_dense(vp, tris, q) @ yn
+            vp[v, d] -= 2e-6
+            fm = xn @ oracle.slp_dense(vp, tris, q) @ yn
+            err = max(err, abs((fp - fm) / 2e-6 - g[v, d]) / scale)
+    print("s=%d: max |adjoint - oracle FD| / max|grad| = %.3e" % (s, err))
+    assert err <= 1e-7
 
 
 def test_autograd_function():

@@ -1,6 +1,7 @@
 """The library's host code (mesh checks, cluster and block trees, Gauss and
 Chebyshev rules, the eigen and QR routines of the recompression, the Green
-cross approximation's host construction) built with g++ under
+cross approximation's host construction, the H-matrix coarsening,
+H-Cholesky factorisation and substitution program) built with g++ under
 AddressSanitizer and UndefinedBehaviorSanitizer and run over meshes of
 several sizes and leaf sizes and over rejected inputs
 (tests/host_asan_driver.cpp).  No device code is built."""
@@ -13,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2001_05523_amd", "csrc")
-HOST_SOURCES = ["host_trees.cpp", "host_linalg.cpp", "gca_host.cpp"]
+HOST_SOURCES = ["host_trees.cpp", "host_linalg.cpp", "gca_host.cpp", "hmatrix.cpp"]
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
