@@ -28,7 +28,8 @@ import numpy as np
 METRIC = "H² G/K matvec ms & HBM GB/s at 2M triangles; mixed vs FP64 at rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "op.hip", "recompress.hip", "panels.hpp", "device.hpp", "op.hpp"]
+KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "op.hip", "transform.hip", "recompress.hip", "panels.hpp",
+                  "device.hpp", "op.hpp"]
 
 
 def sources_digest():
@@ -362,6 +363,63 @@ def ntd_solve(torch, h2b, ops, verts, tris):
     return d
 
 
+def hchol_solves(torch, h2b, sizes):
+    """The paper's preconditioner (coarsening and H-Cholesky factorisation of
+    G to eps_prc, Section 1; eps_prc from the parameter table of Section 5
+    for these sizes) on the Dirichlet-to-Neumann system G t = (M/2 + K) u1 of
+    smaller spheres: setup stages on the host, the factor's storage, the
+    device substitutions per application (HIP events), and CG to 1e-8
+    without a preconditioner, with block Jacobi and with the factor."""
+    import synth
+    res = {}
+    for s, eps in sizes:
+        v, t = synth.octa_sphere(s)
+        G = h2b.Operator(v, t, kernel="slp", leaf=64, order_m=4, q_near=4, recompress_tol=1e-6)
+        K = h2b.Operator(kernel="dlp", leaf=64, order_m=4, q_near=4, recompress_tol=1e-6, mesh=G.mesh)
+        u = torch.tensor(v[:, 0] ** 2 - v[:, 2] ** 2, dtype=torch.float64, device="cuda")
+        b = h2b.dtn_rhs(K, u)
+        t0 = time.perf_counter()
+        P = h2b.HChol(G, eps)
+        build_s = time.perf_counter() - t0
+        info = P.info()
+        z = torch.zeros_like(b)
+        P.apply(b, z)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            P.apply(b, z)
+        e1.record()
+        torch.cuda.synchronize()
+        apply_ms = e0.elapsed_time(e1) / 10
+        d = {"triangles": len(t), "eps_prc": eps, "build_s": round(build_s, 2),
+             "setup_s": {k: round(info[k], 3) for k in ("convert_s", "coarsen_s", "factor_s", "upload_s")},
+             "factor_entries": info["dense_entries"] + info["rk_entries"],
+             "factor_bytes_per_row": round(8.0 * (info["dense_entries"] + info["rk_entries"]) / len(t), 1),
+             "coarse_entries": info["coarse_entries"], "max_rank": info["max_rank"],
+             "substitution_steps": info["steps"], "apply_ms": round(apply_ms, 3),
+             "us_per_step": round(1e3 * apply_ms / max(info["steps"], 1), 3)}
+        sols = {}
+        for name, kw in (("cg", {}), ("block_jacobi", {"precond": "block_jacobi"}),
+                         ("hchol", {"precond": "hchol", "hchol": P})):
+            x = torch.zeros_like(b)
+            r = G.cg(b, x, tol=1e-8, max_iter=3000, **kw)
+            sols[name] = x
+            d[name] = {"iterations": r["iterations"], "status": r["status"], "solve_ms": round(r["solve_ms"], 2)}
+        for name in ("block_jacobi", "hchol"):
+            d[name]["rel_diff_vs_cg"] = float(torch.linalg.norm(sols[name] - sols["cg"]) / torch.linalg.norm(sols["cg"]))
+        res["sphere_%d" % len(t)] = d
+        log("H-Cholesky, %d triangles, eps %.0e: setup %.1f s (%s), factor %.1f MB, apply %.3f ms (%d steps); "
+            "CG %d it %.1f ms, block Jacobi %d it %.1f ms, H-Cholesky %d it %.1f ms" % (
+                len(t), eps, build_s, ", ".join("%s %.2f" % kv for kv in d["setup_s"].items()),
+                8e-6 * d["factor_entries"], apply_ms, info["steps"], d["cg"]["iterations"], d["cg"]["solve_ms"],
+                d["block_jacobi"]["iterations"], d["block_jacobi"]["solve_ms"], d["hchol"]["iterations"],
+                d["hchol"]["solve_ms"]))
+        del P, G, K
+        torch.cuda.empty_cache()
+    return res
+
+
 def gca_solve(torch, h2b, mesh, verts, tris, args):
     """Dirichlet-to-Neumann solve with the Green cross approximation (order
     args.gca_order per face direction, tolerance args.gca_tol) for both G and
@@ -463,6 +521,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows per operator (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the many-RHS / many-mesh section")
+    ap.add_argument("--no-hchol", action="store_true", help="skip the H-Cholesky preconditioner section")
     ap.add_argument("--no-gca-solve", action="store_true",
                     help="skip the solves with GCA operators (about a minute of setup)")
     ap.add_argument("--gca-order", type=int, default=4)
@@ -677,6 +736,9 @@ def main():
 
     if not args.no_batching:
         out["batching"] = batching(torch, h2b, synth, max(5, args.steps // 2))
+
+    if not args.no_hchol:
+        out["hchol_solve"] = hchol_solves(torch, h2b, [(64, 5e-3), (128, 2e-3)])
 
     if not args.no_gca_solve:
         # the benchmark operators make room for the GCA pair
