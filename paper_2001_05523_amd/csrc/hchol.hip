@@ -35,7 +35,8 @@ namespace {
 
 constexpr int XW = 16;  // waves of the executor
 constexpr int MAXDIAG = HProgram::MAXDIAG, TW = HProgram::TW;
-constexpr int T_DIAG = HProgram::T_DIAG, T_COEF = HProgram::T_COEF, I_ROW = HProgram::I_ROW;
+constexpr int T_DIAG = HProgram::T_DIAG, T_COEF = HProgram::T_COEF, T_ROWS = HProgram::T_ROWS;
+constexpr int T_SUM = HProgram::T_SUM, I_ROW = HProgram::I_ROW;
 
 __device__ inline double wave_sum(double v)
 {
@@ -54,10 +55,85 @@ __global__ __launch_bounds__(64 * XW) void k_hchol_run(const int32_t *__restrict
                                                        const double *__restrict__ vals, double *coef, double *y)
 {
     __shared__ double buf[XW][MAXDIAG];
+    __shared__ double part[XW][MAXDIAG];  // per-wave partial sums of a shared task
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int s = s0; s < s1; ++s) {
-        const int t1 = step_ptr[s + 1];
-        for (int ti = step_ptr[s] + wave; ti < t1; ti += XW) {
+        const int t0 = step_ptr[s], t1 = step_ptr[s + 1];
+        // A step of one diagonal-leaf or one row task (most steps near the
+        // leaves) is split over all waves: wave w sums its share of the
+        // columns (diagonal leaf) or of the 16-column pieces of the items
+        // (rows) for every output, and the partial sums are added in order of
+        // w.  The condition is the same for every wave of the workgroup.
+        const int type0 = t1 > t0 ? tasks[(int64_t)t0 * TW] : -1;
+        if (t1 - t0 == 1 && (type0 == T_DIAG || type0 == T_ROWS)) {
+            const int32_t *d = tasks + (int64_t)t0 * TW;
+            const bool diag = d[0] == T_DIAG;
+            const int o = d[1], n = d[2];
+            if (diag) {
+                for (int j = threadIdx.x; j < n; j += 64 * XW) buf[0][j] = y[o + j];
+                __syncthreads();
+                const double *M = vals + off64(d + 3);
+                const int cw = (n + XW - 1) / XW, j0 = min(n, wave * cw), j1 = min(n, j0 + cw);
+                for (int i = lane; i < n; i += 64) {
+                    double acc = 0.0;
+                    int j = j0;
+                    for (; j + 4 <= j1; j += 4) {
+                        double m[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) m[q] = M[(int64_t)(j + q) * n + i];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc += m[q] * buf[0][j + q];
+                    }
+                    for (; j < j1; ++j) acc += M[(int64_t)j * n + i] * buf[0][j];
+                    part[wave][i] = acc;
+                }
+            } else {
+                const int i0 = d[3], i1 = d[4];
+                for (int e = lane; e < n; e += 64) part[wave][e] = 0.0;
+                // pieces of 16 columns over all items, dealt round-robin to the waves
+                int piece = 0;
+                for (int it = i0; it < i1; ++it) {
+                    const int32_t *m = items + (int64_t)it * TW;
+                    const int nin = m[7];
+                    const int np = (nin + 15) / 16;
+                    const int first = (wave - piece % XW + XW) % XW;  // this wave's first piece of the item
+                    if (first < np) {
+                        const double *A = vals + off64(m + 1);
+                        const int ld = m[3], r0 = m[4], x0 = m[6];
+                        const double *src = (m[5] == 0 ? (const double *)y : (const double *)coef) + x0;
+                        const int64_t st = m[0] == I_ROW ? 1 : ld;
+                        for (int e = lane; e < n; e += 64) {
+                            const double *a = m[0] == I_ROW ? A + (int64_t)(r0 + e) * ld : A + r0 + e;
+                            double acc = 0.0;
+                            for (int pc = first; pc < np; pc += XW) {
+                                const int j0 = 16 * pc, j1 = min(nin, j0 + 16);
+                                double av[16], sv[16];
+#pragma unroll
+                                for (int q = 0; q < 16; ++q) {
+                                    const int j = min(j0 + q, j1 - 1);
+                                    av[q] = a[(int64_t)j * st];
+                                    sv[q] = j0 + q < j1 ? src[j] : 0.0;
+                                }
+#pragma unroll
+                                for (int q = 0; q < 16; ++q) acc += av[q] * sv[q];
+                            }
+                            part[wave][e] += acc;
+                        }
+                    }
+                    piece += np;
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += 64 * XW) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < XW; ++w) v += part[w][i];
+                y[o + i] = diag ? v : y[o + i] - v;
+            }
+            __syncthreads();
+            continue;
+        }
+        for (int ti = t0 + wave; ti < t1; ti += XW) {
             const int32_t *d = tasks + (int64_t)ti * TW;
             const int type = d[0];
             if (type == T_DIAG) {
@@ -69,14 +145,31 @@ __global__ __launch_bounds__(64 * XW) void k_hchol_run(const int32_t *__restrict
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 for (int i = lane; i < n; i += 64) {
+                    // 8 independent loads per batch, summed in order of j
                     double acc = 0.0;
-                    for (int j = 0; j < n; ++j) acc += M[(int64_t)j * n + i] * buf[wave][j];
+                    int j = 0;
+                    for (; j + 8 <= n; j += 8) {
+                        double m[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) m[q] = M[(int64_t)(j + q) * n + i];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) acc += m[q] * buf[wave][j + q];
+                    }
+                    for (; j < n; ++j) acc += M[(int64_t)j * n + i] * buf[wave][j];
                     y[o + i] = acc;
                 }
                 // the next task of this wave may overwrite buf
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else if (type == T_SUM) {
+                // coef[dst + p] = sum over the pieces of their partial coefficients, in order
+                const int dst = d[1], src = d[2], np = d[3], k = d[5];
+                for (int p = lane; p < k; p += 64) {
+                    double acc = 0.0;
+                    for (int q = 0; q < np; ++q) acc += coef[src + (int64_t)q * k + p];
+                    coef[dst + p] = acc;
+                }
             } else if (type == T_COEF) {
                 // coef[c .. c+k) = M^T y[yo .. yo+len), M (len x k)
                 const int yo = d[1], len = d[2];
@@ -85,11 +178,14 @@ __global__ __launch_bounds__(64 * XW) void k_hchol_run(const int32_t *__restrict
                 for (int p0 = 0; p0 < k; p0 += 8) {
                     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                     for (int j = lane; j < len; j += 64) {
+                        // all 9 loads issued together (columns past k clamped, weight 0)
                         const double yj = y[yo + j];
-                        const double *m = M + (int64_t)j * k + p0;
+                        const double *m = M + (int64_t)j * k;
+                        double mv[8];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            if (p0 + q < k) acc[q] += m[q] * yj;
+                        for (int q = 0; q < 8; ++q) mv[q] = m[min(p0 + q, k - 1)];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) acc[q] += (p0 + q < k ? mv[q] : 0.0) * yj;
                     }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
@@ -113,13 +209,22 @@ __global__ __launch_bounds__(64 * XW) void k_hchol_run(const int32_t *__restrict
                             const double *A = vals + off64(m + 1);
                             const int ld = m[3], r0 = m[4], x0 = m[6], nin = m[7];
                             const double *src = (m[5] == 0 ? (const double *)y : (const double *)coef) + x0;
-                            if (m[0] == I_ROW) {
-                                const double *a = A + (int64_t)(r0 + e) * ld;
-                                for (int j = 0; j < nin; ++j) acc += a[j] * src[j];
-                            } else {
-                                const double *a = A + r0 + e;
-                                for (int j = 0; j < nin; ++j) acc += a[(int64_t)j * ld] * src[j];
+                            // stride between consecutive j: 1 (rows) or ld (columns);
+                            // 8 independent pairs of loads per batch, summed in order
+                            const double *a = m[0] == I_ROW ? A + (int64_t)(r0 + e) * ld : A + r0 + e;
+                            const int64_t st = m[0] == I_ROW ? 1 : ld;
+                            int j = 0;
+                            for (; j + 8 <= nin; j += 8) {
+                                double av[8], sv[8];
+#pragma unroll
+                                for (int q = 0; q < 8; ++q) {
+                                    av[q] = a[(int64_t)(j + q) * st];
+                                    sv[q] = src[j + q];
+                                }
+#pragma unroll
+                                for (int q = 0; q < 8; ++q) acc += av[q] * sv[q];
                             }
+                            for (; j < nin; ++j) acc += a[(int64_t)j * st] * src[j];
                         }
                         y[o + e] -= acc;
                     }

@@ -7,6 +7,7 @@
 #include "hmatrix.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <functional>
 #include <numeric>
@@ -776,6 +777,7 @@ HStats hmatrix_stats(const HMatrix &H)
 namespace {
 constexpr int TW = HProgram::TW, MAXDIAG = HProgram::MAXDIAG;
 constexpr int T_DIAG = HProgram::T_DIAG, T_COEF = HProgram::T_COEF, T_ROWS = HProgram::T_ROWS;
+constexpr int T_SUM = HProgram::T_SUM;
 constexpr int I_ROW = HProgram::I_ROW, I_COL = HProgram::I_COL;
 
 void put64(std::vector<int32_t> &v, size_t at, int64_t x)
@@ -880,20 +882,48 @@ void hprogram_build(const HMatrix &H, HProgram &F)
         std::vector<int> lv;
         leaves_of(xi, lv);
         if (lv.empty()) return;
+        // coefficients of the low-rank blocks; a long factor is cut into
+        // pieces of COEF_ROWS rows with their own partial coefficients,
+        // summed in a step of their own
         bool any_rk = false;
+        std::vector<std::array<int64_t, 4>> sums;  // destination, first partial, pieces, rank
         for (int i : lv) {
             const HNode &N = H.nodes[i];
             if (N.kind != HNode::RK) continue;
             any_rk = true;
-            const size_t at = task();
-            F.tasks[at] = T_COEF;
-            F.tasks[at + 1] = fw ? T.begin[N.s] : T.begin[N.t];
-            F.tasks[at + 2] = fw ? T.size(N.s) : T.size(N.t);
-            put64(F.tasks, at + 3, fw ? off_b[i] : off_a[i]);
-            F.tasks[at + 5] = N.k;
-            F.tasks[at + 6] = (int32_t)coff[i];
+            const int y0 = fw ? T.begin[N.s] : T.begin[N.t];
+            const int len = fw ? T.size(N.s) : T.size(N.t);
+            const int64_t M = fw ? off_b[i] : off_a[i];
+            const int np = (len + HProgram::COEF_ROWS - 1) / HProgram::COEF_ROWS;
+            int64_t dst = coff[i];
+            if (np > 1) {
+                dst = F.ncoef;
+                F.ncoef += (int64_t)np * N.k;
+                sums.push_back({coff[i], dst, np, N.k});
+            }
+            for (int q = 0; q < np; ++q) {
+                const int r0 = q * HProgram::COEF_ROWS, rl = std::min(HProgram::COEF_ROWS, len - r0);
+                const size_t at = task();
+                F.tasks[at] = T_COEF;
+                F.tasks[at + 1] = y0 + r0;
+                F.tasks[at + 2] = rl;
+                put64(F.tasks, at + 3, M + (int64_t)r0 * N.k);
+                F.tasks[at + 5] = N.k;
+                F.tasks[at + 6] = (int32_t)(dst + (int64_t)q * N.k);
+            }
         }
         if (any_rk) end_step();
+        if (!sums.empty()) {
+            for (const auto &u : sums) {
+                const size_t at = task();
+                F.tasks[at] = T_SUM;
+                F.tasks[at + 1] = (int32_t)u[0];
+                F.tasks[at + 2] = (int32_t)u[1];
+                F.tasks[at + 3] = (int32_t)u[2];
+                F.tasks[at + 5] = (int32_t)u[3];
+            }
+            end_step();
+        }
         const HNode &X = H.nodes[xi];
         std::vector<int> rs;
         tree_leaves(fw ? X.t : X.s, rs);
@@ -951,6 +981,7 @@ void hprogram_build(const HMatrix &H, HProgram &F)
     fwd(H.root);
     F.fw_steps = (int)F.step_ptr.size() - 1;
     bwd(H.root);
+    if (F.ncoef > INT32_MAX) fail(H2B_ENOTSUP, "H-Cholesky: problem too large");
     F.built = true;
 }
 
@@ -988,10 +1019,19 @@ void hprogram_run(const HProgram &F, int64_t n, double *y)
                     for (int j = 0; j < len; ++j) acc += F.vals[M + (int64_t)j * k + p] * y[yo + j];
                     c[q + p] = acc;
                 }
+            } else if (d[0] == T_SUM) {
+                const int dst = d[1], src = d[2], np = d[3], k = d[5];
+                chk(dst >= 0 && dst + k <= F.ncoef && src >= 0 && np > 0 && k > 0 &&
+                    src + (int64_t)np * k <= F.ncoef);
+                for (int p = 0; p < k; ++p) {
+                    double acc = 0.0;
+                    for (int q = 0; q < np; ++q) acc += c[src + (int64_t)q * k + p];
+                    c[dst + p] = acc;
+                }
             } else {
                 chk(d[0] == T_ROWS);
                 const int o = d[1], len = d[2], i0 = d[3], i1 = d[4];
-                chk(o >= 0 && len >= 0 && o + len <= n && i0 >= 0 && i0 <= i1 && i1 <= ni);
+                chk(o >= 0 && len >= 0 && len <= MAXDIAG && o + len <= n && i0 >= 0 && i0 <= i1 && i1 <= ni);
                 for (int e = 0; e < len; ++e) {
                     double acc = 0.0;
                     for (int it = i0; it < i1; ++it) {

@@ -89,6 +89,8 @@ HStats hmatrix_stats(const HMatrix &H);
 //   coefficients   c[q + p] = sum_j M[j k + p] y[yo + j]    [1] yo [2] len [3,4] M [5] k [6] q
 //   rows           y[o + e] -= sum over items of sum_j M(e, j) src[x0 + j]
 //                                                           [1] o [2] len [3] item begin [4] item end
+//   sum            c[d + p] = sum_q c[s + q k + p], q < np     [1] d [2] s [3] np [5] k
+//                  (coefficients of a factor longer than COEF_ROWS rows, computed in pieces)
 // item: [0] 0: M(e, j) = A[(r0 + e) ld + j], 1: M(e, j) = A[j ld + r0 + e];
 //       [1,2] A  [3] ld  [4] r0  [5] src (0: y, 1: c)  [6] x0  [7] number of j.
 // The diagonal leaves store the inverse of their factor (its transpose for
@@ -96,7 +98,8 @@ HStats hmatrix_stats(const HMatrix &H);
 // are the forward substitution, the rest the backward one.
 struct HProgram {
     static constexpr int TW = 8, MAXDIAG = 256;
-    enum : int32_t { T_DIAG = 0, T_COEF = 1, T_ROWS = 2 };
+    static constexpr int COEF_ROWS = 1024;  // rows per coefficient task
+    enum : int32_t { T_DIAG = 0, T_COEF = 1, T_ROWS = 2, T_SUM = 3 };
     enum : int32_t { I_ROW = 0, I_COL = 1 };
     std::vector<double> vals;
     std::vector<int32_t> step_ptr{0}, tasks, items;

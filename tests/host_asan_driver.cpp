@@ -159,10 +159,10 @@ void check_gca(const Tree &T, int m, double eps)
 }
 
 // H-matrix coarsening, H-Cholesky and the substitution program on a
-// symmetric positive definite kernel matrix exp(-|c_i - c_j| / 0.3) + 1e-3 I
+// symmetric positive definite kernel matrix exp(-|c_i - c_j| / 0.3) + shift I
 // over the triangle centroids: the program's solve equals the recursive one,
 // and eps = 0 solves exactly.
-void check_hchol(const Mesh &M, std::shared_ptr<Tree> T, double eps)
+int check_hchol(const Mesh &M, std::shared_ptr<Tree> T, double eps, double shift = 1e-3)
 {
     const int n = (int)T->n;
     std::vector<double> A((size_t)n * n);
@@ -170,7 +170,7 @@ void check_hchol(const Mesh &M, std::shared_ptr<Tree> T, double eps)
         for (int j = 0; j < n; ++j) {
             const int a = T->perm[i], b = T->perm[j];
             const double dx = M.cx[a] - M.cx[b], dy = M.cy[a] - M.cy[b], dz = M.cz[a] - M.cz[b];
-            A[(size_t)i * n + j] = std::exp(-std::sqrt(dx * dx + dy * dy + dz * dz) / 0.3) + (i == j ? 1e-3 : 0.0);
+            A[(size_t)i * n + j] = std::exp(-std::sqrt(dx * dx + dy * dy + dz * dz) / 0.3) + (i == j ? shift : 0.0);
         }
     auto B = build_blocks(T, T, 1.0, false);
     auto H = hmatrix_from_dense(*B, A.data(), eps);
@@ -193,6 +193,9 @@ void check_hchol(const Mesh &M, std::shared_ptr<Tree> T, double eps)
     }
     check(d <= 1e-9 * std::sqrt(nx), "program solve equals the recursive solve");
     if (eps == 0.0) check(std::sqrt(e / nx) <= 1e-8, "exact H-Cholesky solves exactly");
+    int sums = 0;
+    for (size_t t = 0; t < P.tasks.size(); t += HProgram::TW) sums += P.tasks[t] == HProgram::T_SUM;
+    return sums;
 }
 
 }  // namespace
@@ -242,6 +245,13 @@ int main()
             auto M = to_mesh(octa_sphere(6));
             check_hchol(*M, build_tree(M, H2B_P0, leaf), eps);
         }
+    {
+        // 4,232 triangles: coarsened low-rank factors longer than one
+        // coefficient piece (none below about 4,000 triangles; a larger shift
+        // keeps the matrix truncated to 1e-2 definite)
+        auto M = to_mesh(octa_sphere(23));
+        check(check_hchol(*M, build_tree(M, H2B_P0, 32), 1e-2, 1.0) > 0, "coefficients computed in pieces");
+    }
     {
         auto M = to_mesh(plate(12));
         auto R = build_tree(M, H2B_P0, 8);

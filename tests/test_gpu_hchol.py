@@ -57,6 +57,19 @@ def test_device_substitutions_equal_host_solve(s, leaf, eps):
     assert info["steps"] > 0 and info["tasks"] >= info["steps"]
 
 
+def test_device_substitutions_of_a_larger_operator():
+    """8,192 triangles: low-rank factors longer than one coefficient piece
+    (1,024 rows), computed in pieces and summed; device equals host."""
+    h = _lib()
+    v, t = synth.octa_sphere(32)
+    op = h.Operator(v, t, kernel="slp", leaf=32, order_m=4, q_near=4, recompress_tol=1e-6)
+    P = h.HChol(op, 1e-3)
+    r = synth.random_vector(len(t), 27)
+    zh = P.solve_host(r)
+    zd = _apply(P, r)
+    assert np.linalg.norm(zd - zh) <= 1e-12 * np.linalg.norm(zh)
+
+
 def test_operator_without_far_field_gives_the_cholesky_solve():
     """Far field disabled: the converted H-matrix is the lower triangle of
     the dense Galerkin G of the oracle (entries equal to 1e-10), so with
@@ -96,6 +109,28 @@ def test_operator_factor_against_oracle_h2(tol):
     err = np.linalg.norm(z - zref) / np.linalg.norm(zref)
     print("recompress_tol %.0e: %.2e" % (tol, err))
     assert err <= bound
+
+
+def test_factor_of_gca_operator_inverts_the_product():
+    """The Green cross approximation keeps its bases in the same panels
+    (V_t^T per leaf, [E_1^T | E_2^T] per parent), so its operator converts
+    the same way: with eps = 0, G z for z = (L L^T)^{-1} r gives back r up to
+    the asymmetry of the quadrature of touching pairs (about 1e-7 relative,
+    times the condition number of G here, about 100)."""
+    torch = _torch()
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    op = h.Operator(v, t, kernel="slp", leaf=16, order_m=3, q_near=4, gca_tol=1e-6, symmetric_near=False)
+    P = h.HChol(op, 0.0)
+    r = _dev(synth.random_vector(len(t), 26))
+    z = torch.zeros_like(r)
+    P.apply(r, z)
+    back = torch.zeros_like(r)
+    op.matvec(z, back)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(back - r) / torch.linalg.norm(r))
+    print("GCA: |G z - r| / |r| = %.2e" % err)
+    assert err <= 1e-4
 
 
 def test_preconditioned_cg_on_the_device():
