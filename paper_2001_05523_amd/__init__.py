@@ -346,6 +346,29 @@ class Operator:
                           _vp(y.data_ptr()), ldy, nrhs, _stream_ptr(stream)))
         return y
 
+    def _product(self, x, trans):
+        import torch
+        if not isinstance(x, torch.Tensor) or x.dim() not in (1, 2):
+            raise TypeError("x must be a 1-D or 2-D float64 CUDA tensor")
+        nout = self.shape[1] if trans else self.shape[0]
+        if x.dim() == 1:
+            y = torch.zeros(nout, dtype=torch.float64, device=x.device)
+        else:
+            if x.stride(0) != 1:
+                x = x.t().contiguous().t()  # columns contiguous
+            y = torch.zeros((x.shape[1], nout), dtype=torch.float64, device=x.device).t()
+        return self.matvec(x, y, trans=trans)
+
+    def __matmul__(self, x):
+        """A @ x as a new tensor: x a vector, or a matrix whose columns are
+        right-hand sides (at most 64)."""
+        return self._product(x, False)
+
+    @property
+    def T(self):
+        """The transposed operator: op.T @ x computes A^T x."""
+        return _Transposed(self)
+
     def tune(self, nrhs, stream=None):
         """Autotune the many-right-hand-side coupling product; returns its time in us."""
         best = _dbl()
@@ -448,6 +471,17 @@ class Operator:
         if getattr(self, "handle", None) and not _exiting[0]:
             _destroy(self.handle)
             self.handle = None
+
+
+class _Transposed:
+    """A^T of an Operator, for op.T @ x."""
+
+    def __init__(self, op):
+        self.op = op
+        self.shape = (op.shape[1], op.shape[0])
+
+    def __matmul__(self, x):
+        return self.op._product(x, True)
 
 
 class HChol:

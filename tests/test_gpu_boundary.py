@@ -79,3 +79,28 @@ def test_slp_bilinear_against_oracle():
     with pytest.raises(h.H2BError):
         h._check(h.h2b_slp_bilinear(op.handle, h._vp(X.data_ptr()), h._vp(Y.data_ptr()), h._vp(X.data_ptr()),
                                     h._vp(b.data_ptr()), None))
+
+
+def test_matmul_operator_and_transpose():
+    """op @ x and op.T @ x (the binding's product notation) equal the
+    library's products, for a vector and for a block of right-hand sides
+    given row-major (the binding makes its columns contiguous)."""
+    import torch
+    h = _lib()
+    v, t = synth.octa_sphere(8)
+    K = h.Operator(v, t, kernel="dlp", leaf=16, order_m=3, q_near=4)
+    x = torch.tensor(synth.random_vector(K.shape[1], 71), device="cuda")
+    y = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
+    K.matvec(x, y)
+    assert torch.equal(K @ x, y)
+    w = torch.tensor(synth.random_vector(K.shape[0], 72), device="cuda")
+    z = torch.zeros(K.shape[1], dtype=torch.float64, device="cuda")
+    K.matvec(w, z, trans=True)
+    assert torch.equal(K.T @ w, z) and K.T.shape == (K.shape[1], K.shape[0])
+    X = torch.tensor(synth.random_vector(K.shape[1], 73, cols=5), device="cuda")  # row-major
+    Y = K @ X
+    assert Y.shape == (K.shape[0], 5)
+    for c in range(5):
+        yc = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
+        K.matvec(X[:, c].contiguous(), yc)
+        assert float((Y[:, c] - yc).abs().max()) <= 1e-12 * float(yc.abs().max())
