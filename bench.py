@@ -28,7 +28,7 @@ import numpy as np
 METRIC = "H² G/K matvec ms & HBM GB/s at 2M triangles; mixed vs FP64 at rel err ≤1e-5"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "op.hip", "transform.hip", "recompress.hip", "panels.hpp",
+KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "symcpl.hip", "op.hip", "transform.hip", "recompress.hip", "panels.hpp",
                   "device.hpp", "op.hpp"]
 
 
@@ -75,7 +75,11 @@ def alg_bytes(info, fsz, trans=False):
                 + 20 * info["near_sym_corrections"] + 8 * nout + 8 * (nin + 2 * nout))
     else:
         near = 8 * info["near_entries"] + 8 * (nin + 2 * nout)
-    cpl = fsz * info["coupling_entries"] + fsz * (hin + 2 * hout)
+    if info.get("cpl_sym_entries", 0) > 0:
+        # once-per-pair coupling: entries, column sums written and read back
+        cpl = 8 * info["cpl_sym_entries"] + 16 * info["cpl_sym_columns"] + 8 * (hin + 2 * hout)
+    else:
+        cpl = fsz * info["coupling_entries"] + fsz * (hin + 2 * hout)
     bases = fsz * (info["row_basis_entries"] + info["col_basis_entries"])
     total = near + cpl + bases + vec
     return dict(total=total, near=near, coupling=cpl, bases=bases)
@@ -84,6 +88,9 @@ def alg_bytes(info, fsz, trans=False):
 def kernel_name(op, phase, info):
     """Kernels that make up a product phase, for the roofline record."""
     if phase == "coupling":
+        if info.get("cpl_sym_entries", 0) > 0:
+            return ("%s coupling stored once per pair of clusters, A x and A^T x launches (k_cplsym "
+                    "+ k_cplreduce)" % op)
         return "%s coupling, A x and A^T x launches (k_rowpanel<double, double, double, 2, 1, 4>)" % op
     if info["near_sym_entries"] > 0:
         return ("%s nearfield stored once per pair of leaves, A x and A^T x launches (k_nearsym<false|true> "
@@ -214,6 +221,7 @@ def batching(torch, h2b, synth, reps):
         # the merged batch reads the full nearfield of G (not the once-per-pair form)
         inf = dict(op.info())
         inf["near_sym_entries"] = 0
+        inf["cpl_sym_entries"] = 0
         abytes += alg_bytes(inf, 4)["total"]
 
     def timed(fn, n):

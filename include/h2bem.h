@@ -188,7 +188,11 @@ typedef struct {
                                N_ts, s > t) plus the sparse difference G_ji - G_ij of the touching
                                pairs across leaves; the single-vector products G x and G^T x then
                                read about half the nearfield bytes (0.53x the nearfield storage
-                               extra).  Ignored otherwise. */
+                               extra).  With stored FP64 interpolation couplings of rank at most
+                               64 (no gca_tol, no recompute_coupling) the coupling matrices are
+                               also stored once per pair of clusters (S_ts for s > t; S_st is its
+                               transpose), which halves the coupling bytes of those products
+                               (0.5x the coupling storage extra).  Ignored otherwise. */
     double gca_tol;         /* > 0: far field by the Green cross approximation of Section 4
                                instead of interpolation: order_m Gauss points per direction on each
                                face of the auxiliary box omega_t (B_t widened by its largest side),
@@ -245,6 +249,8 @@ typedef struct {
     int64_t near_sym_columns;      /* its panel columns (one column sum each per product) */
     int64_t near_sym_corrections;  /* touching pairs across leaves (corrections per product) */
     int64_t coupling_evals;        /* kernel evaluations per product (recompute_coupling; else 0) */
+    int64_t cpl_sym_entries;       /* entries of the once-per-pair coupling of G (0 if none) */
+    int64_t cpl_sym_columns;       /* its panel columns (one column sum each per product) */
 } h2b_op_stats;
 
 h2b_status h2b_op_info(h2b_op op, h2b_op_stats *out);

@@ -53,7 +53,7 @@ class h2b_op_stats(ctypes.Structure):
                 ("max_rank_row", _i32), ("max_rank_col", _i32),
                 ("mean_rank_row", _dbl), ("mean_rank_col", _dbl), ("bytes_transposed", _i64),
                 ("near_sym_entries", _i64), ("near_sym_columns", _i64), ("near_sym_corrections", _i64),
-                ("coupling_evals", _i64)]
+                ("coupling_evals", _i64), ("cpl_sym_entries", _i64), ("cpl_sym_columns", _i64)]
 
 
 class h2b_cg_params(ctypes.Structure):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 OUT_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(OUT_DIR, "libh2bem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["host_trees.cpp", "host_linalg.cpp", "kernels.hip", "kernels_mrhs.hip", "op.hip", "recompress.hip", "batch.hip", "batch_merged.hip", "symnear.hip", "krylov.hip", "gca.hip", "gca_host.cpp", "recompute.hip", "transform.hip", "hmatrix.cpp", "hchol.hip", "capi.cpp"]
+SOURCES = ["host_trees.cpp", "host_linalg.cpp", "kernels.hip", "kernels_mrhs.hip", "op.hip", "recompress.hip", "batch.hip", "batch_merged.hip", "symnear.hip", "symcpl.hip", "krylov.hip", "gca.hip", "gca_host.cpp", "recompute.hip", "transform.hip", "hmatrix.cpp", "hchol.hip", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

@@ -414,6 +414,11 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols && op->near.max_nrows <= 64 &&
         op->near.ngroups() > 0)
         make_symmetric_near(*op, st);
+    // the far field of G once per pair: stored FP64 couplings of interpolation
+    // (symmetric by construction), ranks of at most 64
+    if (op->sym && !gca && !op->recompute && p.farfield_dtype == H2B_F64 && op->rowb == op->colb &&
+        op->cpl.max_nrows <= 64 && op->cpl.ngroups() > 0)
+        make_symmetric_coupling(*op, st);
 
     // work vectors
     const size_t wsz = basis_size(p.farfield_dtype);
@@ -600,6 +605,15 @@ static void product_piece(Op &op, const Work &w, int trans, double alpha, const 
         if constexpr (std::is_same<F, double>::value) {
             if (op.recompute) {
                 recompute_coupling(op, trans, 1, xhat, yhat, w.xt, w.yt, st);
+                mark(3);
+                backward<F>(Bout, yhat, yp, st);
+                mark(4);
+                break;
+            }
+        }
+        if constexpr (std::is_same<F, double>::value && std::is_same<C, double>::value) {
+            if (op.symcpl && w.sym) {
+                symmetric_coupling_product(op, xhat, yhat, st);
                 mark(3);
                 backward<F>(Bout, yhat, yp, st);
                 mark(4);
@@ -1048,6 +1062,10 @@ void op_stats(const Op &op, h2b_op_stats &s)
         s.near_sym_entries = op.sym->P.total;
         s.near_sym_columns = op.sym->col_base.back();
         s.near_sym_corrections = op.sym->ncorr;
+    }
+    if (op.symcpl) {
+        s.cpl_sym_entries = op.symcpl->P.total;
+        s.cpl_sym_columns = op.symcpl->col_base.back();
     }
     s.bytes_transposed = op.has_R ? op.near_R.total * 8 + (op.recompute ? 0 : op.cpl_R.total) *
                                                               (int64_t)coupling_size(op.params.farfield_dtype)

@@ -82,6 +82,23 @@ struct SymNear {
     int64_t ncorr = 0;
 };
 
+// Far field of G stored once per pair of clusters: for every row cluster t
+// the panel [S_ts for the farfield clusters s > t] (S_st = S_ts^T, one basis
+// for rows and columns).  One pass adds the row sums to y^_t and writes the
+// column sums S_ts^T x^_t to `colsum`; a second launch adds those per cluster.
+struct SymCpl {
+    RowPanels P;                    // groups = row clusters, segments = farfield clusters s > t
+    DevMem vals;
+    DevMem colsum;                  // one column sum per panel column
+    std::vector<int64_t> col_base;  // first colsum entry of each group
+    ColPanels red;                  // per cluster u: the blocks (t, u), t < u, as colsum offsets
+    std::vector<int64_t> cp_src, cp_dst;  // copy of the stored blocks out of the full coupling panels
+    std::vector<int32_t> cp_src_ld, cp_dst_ld, cp_rows, cp_cols;
+    DevMem desc;
+    const int64_t *d_col_base = nullptr, *d_cp_src = nullptr, *d_cp_dst = nullptr;
+    const int32_t *d_cp_src_ld = nullptr, *d_cp_dst_ld = nullptr, *d_cp_rows = nullptr, *d_cp_cols = nullptr;
+};
+
 struct Op {
     std::shared_ptr<const Blocks> blocks;
     h2b_kernel kernel = H2B_SLP;
@@ -102,6 +119,7 @@ struct Op {
     DevMem near_R_vals, cpl_R_vals;
     bool has_R = false;
     std::unique_ptr<SymNear> sym;           // params.symmetric_near for G on one tree
+    std::unique_ptr<SymCpl> symcpl;         // the same for G's stored FP64 coupling
     DevMem xp, yp, xhat, yhat;              // product work vectors
     DevMem ypn;                             // near-field output (summed with yp by the scatter)
     DevMem xpb, ypb, xhatb, yhatb, ypbn;    // block work vectors (many right-hand sides)
@@ -170,6 +188,10 @@ void make_transposed_copies(Op &op, hipStream_t st);
 void make_symmetric_near(Op &op, hipStream_t st);
 // ypn += N x (trans = 0) or N^T x (trans = 1) from the once-per-pair storage.
 void symmetric_near_product(const Op &op, int trans, const double *xp, double *ypn, hipStream_t st);
+// Structure (first call) and values of the once-per-pair coupling of G.
+void make_symmetric_coupling(Op &op, hipStream_t st);
+// yhat += S xhat (= S^T xhat) from the once-per-pair coupling.
+void symmetric_coupling_product(const Op &op, const double *xhat, double *yhat, hipStream_t st);
 void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
                         int nrhs);
 // Allocates what a product with nrhs right-hand sides needs (before a capture).
