@@ -77,7 +77,7 @@ def alg_bytes(info, fsz, trans=False):
         near = 8 * info["near_entries"] + 8 * (nin + 2 * nout)
     if info.get("cpl_sym_entries", 0) > 0:
         # once-per-pair coupling: entries, column sums written and read back
-        cpl = 8 * info["cpl_sym_entries"] + 16 * info["cpl_sym_columns"] + 8 * (hin + 2 * hout)
+        cpl = fsz * info["cpl_sym_entries"] + 2 * fsz * info["cpl_sym_columns"] + fsz * (hin + 2 * hout)
     else:
         cpl = fsz * info["coupling_entries"] + fsz * (hin + 2 * hout)
     bases = fsz * (info["row_basis_entries"] + info["col_basis_entries"])

@@ -414,9 +414,9 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols && op->near.max_nrows <= 64 &&
         op->near.ngroups() > 0)
         make_symmetric_near(*op, st);
-    // the far field of G once per pair: stored FP64 couplings of interpolation
-    // (symmetric by construction), ranks of at most 64
-    if (op->sym && !gca && !op->recompute && p.farfield_dtype == H2B_F64 && op->rowb == op->colb &&
+    // the far field of G once per pair: stored FP64 or FP32 couplings of
+    // interpolation (symmetric by construction), ranks of at most 64
+    if (op->sym && !gca && !op->recompute && p.farfield_dtype != H2B_BF16 && op->rowb == op->colb &&
         op->cpl.max_nrows <= 64 && op->cpl.ngroups() > 0)
         make_symmetric_coupling(*op, st);
 
@@ -611,7 +611,7 @@ static void product_piece(Op &op, const Work &w, int trans, double alpha, const 
                 break;
             }
         }
-        if constexpr (std::is_same<F, double>::value && std::is_same<C, double>::value) {
+        if constexpr (std::is_same<F, C>::value) {
             if (op.symcpl && w.sym) {
                 symmetric_coupling_product(op, xhat, yhat, st);
                 mark(3);

@@ -97,6 +97,7 @@ struct SymCpl {
     DevMem desc;
     const int64_t *d_col_base = nullptr, *d_cp_src = nullptr, *d_cp_dst = nullptr;
     const int32_t *d_cp_src_ld = nullptr, *d_cp_dst_ld = nullptr, *d_cp_rows = nullptr, *d_cp_cols = nullptr;
+    bool f32 = false;               // values and column sums in FP32 (FP32 far field), else FP64
 };
 
 struct Op {
@@ -119,7 +120,7 @@ struct Op {
     DevMem near_R_vals, cpl_R_vals;
     bool has_R = false;
     std::unique_ptr<SymNear> sym;           // params.symmetric_near for G on one tree
-    std::unique_ptr<SymCpl> symcpl;         // the same for G's stored FP64 coupling
+    std::unique_ptr<SymCpl> symcpl;         // the same for G's stored FP64 or FP32 coupling
     DevMem xp, yp, xhat, yhat;              // product work vectors
     DevMem ypn;                             // near-field output (summed with yp by the scatter)
     DevMem xpb, ypb, xhatb, yhatb, ypbn;    // block work vectors (many right-hand sides)
@@ -190,8 +191,8 @@ void make_symmetric_near(Op &op, hipStream_t st);
 void symmetric_near_product(const Op &op, int trans, const double *xp, double *ypn, hipStream_t st);
 // Structure (first call) and values of the once-per-pair coupling of G.
 void make_symmetric_coupling(Op &op, hipStream_t st);
-// yhat += S xhat (= S^T xhat) from the once-per-pair coupling.
-void symmetric_coupling_product(const Op &op, const double *xhat, double *yhat, hipStream_t st);
+// yhat += S xhat (= S^T xhat) from the once-per-pair coupling (T: the far-field precision).
+template <typename T> void symmetric_coupling_product(const Op &op, const T *xhat, T *yhat, hipStream_t st);
 void check_product_args(const Op &op, int trans, const double *x, int64_t ldx, const double *y, int64_t ldy,
                         int nrhs);
 // Allocates what a product with nrhs right-hand sides needs (before a capture).

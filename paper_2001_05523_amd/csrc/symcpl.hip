@@ -8,7 +8,8 @@
 // and the column sums S_ts^T x^_t, which go to a scratch vector, and a
 // second launch (k_cplreduce) adds the column sums per cluster s.  The
 // single-vector products G x and G^T x both use it (the far field of G is
-// symmetric); the result equals the full coupling product to rounding.
+// symmetric); the result equals the full coupling product to rounding.  FP64
+// and FP32 far fields (values, coefficients and sums in that precision).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,7 +26,7 @@ constexpr int CS_MAXSEG = 256;  // segment descriptors held in LDS
 constexpr int CS_NB = 4;        // column blocks of 64 per pass (256 columns)
 constexpr int CS_RW = 4;        // rows per step
 
-__device__ inline double wave_sum_c(double v)
+template <typename T> __device__ inline T wave_sum_c(T v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -40,11 +41,12 @@ __device__ inline double wave_sum_c(double v)
 // ragged tail is clamped to the last column with weight 0), adds them into the
 // row sums (one wave reduction per row) and, weighted with x^_t of the rows,
 // into the column sums.  Rows past the end repeat the last row with weight 0.
-__global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const double *__restrict__ vals,
-                                               const double *__restrict__ xhat, double *__restrict__ yhat,
-                                               double *__restrict__ colsum, const int64_t *__restrict__ col_base)
+template <typename T>
+__global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const T *__restrict__ vals,
+                                               const T *__restrict__ xhat, T *__restrict__ yhat,
+                                               T *__restrict__ colsum, const int64_t *__restrict__ col_base)
 {
-    __shared__ double xt[64 + CS_RW], racc[64];
+    __shared__ T xt[64 + CS_RW], racc[64];
     __shared__ int32_t lc0[CS_MAXSEG], lin[CS_MAXSEG];
     const int g = blockIdx.x, lane = threadIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
@@ -60,19 +62,19 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const double *__re
         c0s = lc0;
         ins = lin;
     }
-    for (int r = lane; r < 64 + CS_RW; r += 64) xt[r] = r < nr ? xhat[ob + r] : 0.0;
-    racc[lane] = 0.0;
+    for (int r = lane; r < 64 + CS_RW; r += 64) xt[r] = r < nr ? xhat[ob + r] : T(0);
+    racc[lane] = T(0);
     __syncthreads();
     const int64_t cb = col_base[g];
     const int clast = nc - 1;
     for (int p0 = 0; p0 < nc; p0 += 64 * CS_NB) {
         const int nb = min(CS_NB, (nc - p0 + 63) >> 6);  // column blocks holding columns (uniform)
-        double xg[CS_NB], cs[CS_NB];
+        T xg[CS_NB], cs[CS_NB];
 #pragma unroll
         for (int b = 0; b < CS_NB; ++b) {
             const int c = p0 + lane + 64 * b;
-            cs[b] = 0.0;
-            xg[b] = 0.0;
+            cs[b] = T(0);
+            xg[b] = T(0);
             if (c < nc) {
                 int lo = 0, hi = nseg - 1;  // last segment starting at or before c
                 while (lo < hi) {
@@ -86,19 +88,19 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const double *__re
             }
         }
         for (int r = 0; r < nr; r += CS_RW) {
-            double a[CS_RW][CS_NB];
+            T a[CS_RW][CS_NB];
 #pragma unroll
             for (int i = 0; i < CS_RW; ++i) {
-                const double *row = vals + off + (int64_t)min(r + i, nr - 1) * nc;
+                const T *row = vals + off + (int64_t)min(r + i, nr - 1) * nc;
 #pragma unroll
                 for (int b = 0; b < CS_NB; ++b)
-                    a[i][b] = b < nb ? __builtin_nontemporal_load(row + min(p0 + lane + 64 * b, clast)) : 0.0;
+                    a[i][b] = b < nb ? __builtin_nontemporal_load(row + min(p0 + lane + 64 * b, clast)) : T(0);
             }
-            double s[CS_RW];
+            T s[CS_RW];
 #pragma unroll
             for (int i = 0; i < CS_RW; ++i) {
-                const double w = xt[r + i];  // 0 past the last row
-                s[i] = 0.0;
+                const T w = xt[r + i];  // 0 past the last row
+                s[i] = T(0);
 #pragma unroll
                 for (int b = 0; b < CS_NB; ++b) {
                     s[i] += a[i][b] * xg[b];  // xg is 0 past the last column
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const double *__re
             }
 #pragma unroll
             for (int i = 0; i < CS_RW; ++i) {
-                const double v = wave_sum_c(s[i]);
+                const T v = wave_sum_c(s[i]);
                 if (lane == 0 && r + i < nr) racc[r + i] += v;
             }
         }
@@ -123,20 +125,21 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const double *__re
 
 // One wave per cluster u: y^_u += the column sums of the stored blocks (t, u),
 // in the order of the blocks, 8 loads per batch.
-__global__ __launch_bounds__(64) void k_cplreduce(ColPanelDev red, const double *__restrict__ colsum,
-                                                  double *__restrict__ yhat)
+template <typename T>
+__global__ __launch_bounds__(64) void k_cplreduce(ColPanelDev red, const T *__restrict__ colsum,
+                                                  T *__restrict__ yhat)
 {
     const int u = blockIdx.x;
     const int ob = red.out_begin[u], ol = red.out_len[u];
     const int b0 = red.blk_ptr[u], b1 = red.blk_ptr[u + 1];
     for (int j = threadIdx.x; j < ol; j += 64) {
-        double acc = 0.0;
+        T acc = T(0);
         for (int b = b0; b < b1; b += 8) {
-            double v[8];
+            T v[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double x = colsum[red.b_val_off[min(b + q, b1 - 1)] + j];
-                v[q] = b + q < b1 ? x : 0.0;
+                const T x = colsum[red.b_val_off[min(b + q, b1 - 1)] + j];
+                v[q] = b + q < b1 ? x : T(0);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc += v[q];
@@ -145,13 +148,14 @@ __global__ __launch_bounds__(64) void k_cplreduce(ColPanelDev red, const double 
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_copy_cpl(const int64_t *__restrict__ src_off,
                                                   const int32_t *__restrict__ src_ld,
                                                   const int64_t *__restrict__ dst_off,
                                                   const int32_t *__restrict__ dst_ld,
                                                   const int32_t *__restrict__ rows,
-                                                  const int32_t *__restrict__ cols, const double *__restrict__ src,
-                                                  double *__restrict__ dst)
+                                                  const int32_t *__restrict__ cols, const T *__restrict__ src,
+                                                  T *__restrict__ dst)
 {
     const int b = blockIdx.x;
     const int nr = rows[b], nc = cols[b];
@@ -226,32 +230,42 @@ void make_symmetric_coupling(Op &op, hipStream_t st)
         pk.add(S->cp_rows, const_cast<int32_t **>(&S->d_cp_rows));
         pk.add(S->cp_cols, const_cast<int32_t **>(&S->d_cp_cols));
         pk.upload(S->desc, st);
-        S->vals.alloc(sizeof(double) * std::max<int64_t>(S->P.total, 1));
-        S->colsum.alloc(sizeof(double) * std::max<int64_t>(S->col_base.back(), 1));
+        S->f32 = op.params.farfield_dtype == H2B_F32;
+        const size_t es = S->f32 ? sizeof(float) : sizeof(double);
+        S->vals.alloc(es * std::max<int64_t>(S->P.total, 1));
+        S->colsum.alloc(es * std::max<int64_t>(S->col_base.back(), 1));
         S->cp_src.clear();
         S->cp_dst.clear();
         op.symcpl = std::move(S);
     }
     SymCpl &S = *op.symcpl;
     const int nblk = (int)S.cp_rows.size();
-    if (nblk > 0)
-        hipLaunchKernelGGL(k_copy_cpl, dim3(nblk), dim3(256), 0, st, S.d_cp_src, S.d_cp_src_ld, S.d_cp_dst,
+    if (nblk > 0 && S.f32)
+        hipLaunchKernelGGL(k_copy_cpl<float>, dim3(nblk), dim3(256), 0, st, S.d_cp_src, S.d_cp_src_ld, S.d_cp_dst,
+                           S.d_cp_dst_ld, S.d_cp_rows, S.d_cp_cols, op.cpl_vals.as<float>(), S.vals.as<float>());
+    else if (nblk > 0)
+        hipLaunchKernelGGL(k_copy_cpl<double>, dim3(nblk), dim3(256), 0, st, S.d_cp_src, S.d_cp_src_ld, S.d_cp_dst,
                            S.d_cp_dst_ld, S.d_cp_rows, S.d_cp_cols, op.cpl_vals.as<double>(), S.vals.as<double>());
     hip_check(hipGetLastError(), "coupling copy launch");
     hip_check(hipStreamSynchronize(st), "once-per-pair far field");
 }
 
-void symmetric_coupling_product(const Op &op, const double *xhat, double *yhat, hipStream_t st)
+template <typename T>
+void symmetric_coupling_product(const Op &op, const T *xhat, T *yhat, hipStream_t st)
 {
     const SymCpl &S = *op.symcpl;
-    double *cs = S.colsum.as<double>();
+    if (S.f32 != std::is_same<T, float>::value) fail(H2B_EINVAL, "once-per-pair coupling of another precision");
+    T *cs = S.colsum.as<T>();
     if (S.P.ngroups() > 0)
-        hipLaunchKernelGGL(k_cplsym, dim3(S.P.ngroups()), dim3(64), 0, st, S.P.dev, S.vals.as<double>(), xhat, yhat,
+        hipLaunchKernelGGL(k_cplsym<T>, dim3(S.P.ngroups()), dim3(64), 0, st, S.P.dev, S.vals.as<T>(), xhat, yhat,
                            cs, S.d_col_base);
     hip_check(hipGetLastError(), "once-per-pair coupling launch");
     if (S.red.ngroups() > 0)
-        hipLaunchKernelGGL(k_cplreduce, dim3(S.red.ngroups()), dim3(64), 0, st, S.red.dev, cs, yhat);
+        hipLaunchKernelGGL(k_cplreduce<T>, dim3(S.red.ngroups()), dim3(64), 0, st, S.red.dev, cs, yhat);
     hip_check(hipGetLastError(), "coupling column-sum launch");
 }
+
+template void symmetric_coupling_product<double>(const Op &, const double *, double *, hipStream_t);
+template void symmetric_coupling_product<float>(const Op &, const float *, float *, hipStream_t);
 
 }  // namespace h2b
