@@ -188,11 +188,12 @@ typedef struct {
                                N_ts, s > t) plus the sparse difference G_ji - G_ij of the touching
                                pairs across leaves; the single-vector products G x and G^T x then
                                read about half the nearfield bytes (0.53x the nearfield storage
-                               extra).  With stored FP64 or FP32 interpolation couplings of rank
-                               at most 64 (no gca_tol, no recompute_coupling) the coupling matrices are
-                               also stored once per pair of clusters (S_ts for s > t; S_st is its
-                               transpose), which halves the coupling bytes of those products
-                               (0.5x the coupling storage extra).  Ignored otherwise. */
+                               extra).  With stored FP64 or FP32 couplings (interpolation or
+                               gca_tol; not recompute_coupling) of rank at most 256 the coupling
+                               matrices are also stored once per pair of clusters (S_ts for s > t;
+                               S_st is its transpose to rounding), which halves the coupling bytes
+                               of those products (0.5x the coupling storage extra).  Ignored
+                               otherwise. */
     double gca_tol;         /* > 0: far field by the Green cross approximation of Section 4
                                instead of interpolation: order_m Gauss points per direction on each
                                face of the auxiliary box omega_t (B_t widened by its largest side),

@@ -414,10 +414,11 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (p.symmetric_near && kernel == H2B_SLP && blocks->rows == blocks->cols && op->near.max_nrows <= 64 &&
         op->near.ngroups() > 0)
         make_symmetric_near(*op, st);
-    // the far field of G once per pair: stored FP64 or FP32 couplings of
-    // interpolation (symmetric by construction), ranks of at most 64
-    if (op->sym && !gca && !op->recompute && p.farfield_dtype != H2B_BF16 && op->rowb == op->colb &&
-        op->cpl.max_nrows <= 64 && op->cpl.ngroups() > 0)
+    // the far field of G once per pair: stored FP64 or FP32 couplings, kernel
+    // values at interpolation points or quadrature entries of well-separated
+    // pivot triangles (both symmetric to rounding)
+    if (op->sym && !op->recompute && p.farfield_dtype != H2B_BF16 && op->rowb == op->colb &&
+        op->cpl.max_nrows <= SYMCPL_MAX_RANK && op->cpl.ngroups() > 0)
         make_symmetric_coupling(*op, st);
 
     // work vectors

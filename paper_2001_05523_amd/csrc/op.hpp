@@ -82,6 +82,8 @@ struct SymNear {
     int64_t ncorr = 0;
 };
 
+constexpr int SYMCPL_MAX_RANK = 256;  // largest cluster rank of the once-per-pair coupling
+
 // Far field of G stored once per pair of clusters: for every row cluster t
 // the panel [S_ts for the farfield clusters s > t] (S_st = S_ts^T, one basis
 // for rows and columns).  One pass adds the row sums to y^_t and writes the

@@ -33,7 +33,7 @@ template <typename T> __device__ inline T wave_sum_c(T v)
     return v;
 }
 
-// One wave per stored row cluster t (rank at most 64).  A pass covers 256
+// One wave per stored row cluster t (rank at most SYMCPL_MAX_RANK).  A pass covers 256
 // panel columns, one per lane and column block; the inputs x^_s of its columns
 // are gathered once (segment by binary search) and the column sums stay in
 // registers.  Each step loads 4 rows of the pass (4 x 4 non-temporal loads in
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const T *__restric
                                                const T *__restrict__ xhat, T *__restrict__ yhat,
                                                T *__restrict__ colsum, const int64_t *__restrict__ col_base)
 {
-    __shared__ T xt[64 + CS_RW], racc[64];
+    __shared__ T xt[SYMCPL_MAX_RANK + CS_RW], racc[SYMCPL_MAX_RANK];
     __shared__ int32_t lc0[CS_MAXSEG], lin[CS_MAXSEG];
     const int g = blockIdx.x, lane = threadIdx.x;
     const int nr = d.nrows[g], nc = d.ncols[g];
@@ -62,8 +62,10 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const T *__restric
         c0s = lc0;
         ins = lin;
     }
-    for (int r = lane; r < 64 + CS_RW; r += 64) xt[r] = r < nr ? xhat[ob + r] : T(0);
-    racc[lane] = T(0);
+    for (int r = lane; r < nr + CS_RW; r += 64) {
+        xt[r] = r < nr ? xhat[ob + r] : T(0);  // 0 on the rows past the end
+        racc[min(r, SYMCPL_MAX_RANK - 1)] = T(0);
+    }
     __syncthreads();
     const int64_t cb = col_base[g];
     const int clast = nc - 1;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(64) void k_cplsym(RowPanelDev d, const T *__restric
         }
     }
     __syncthreads();
-    if (lane < nr) yhat[ob + lane] += racc[lane];
+    for (int r = lane; r < nr; r += 64) yhat[ob + r] += racc[r];
 }
 
 // One wave per cluster u: y^_u += the column sums of the stored blocks (t, u),
@@ -199,7 +201,8 @@ void make_symmetric_coupling(Op &op, hipStream_t st)
             }
             S->P.end_group();
         }
-        if (S->P.max_nrows > 64) fail(H2B_ENOTSUP, "the once-per-pair far field needs ranks of at most 64");
+        if (S->P.max_nrows > SYMCPL_MAX_RANK)
+            fail(H2B_ENOTSUP, "the once-per-pair far field needs ranks of at most " + std::to_string(SYMCPL_MAX_RANK));
         for (size_t b = 0; b < blk_group.size(); ++b) {
             S->cp_dst.push_back(S->P.val_off[blk_group[b]] + blk_c0[b]);
             S->cp_dst_ld.push_back(S->P.ncols[blk_group[b]]);

@@ -56,6 +56,26 @@ def test_gca_product_matches_oracle_gca(m, eps):
         assert _rel(y, (A.T if trans else A) @ x) <= 1e-10, (m, eps, trans)
 
 
+def test_gca_once_per_pair_coupling_matches_full():
+    """The cross approximation's couplings of G are entries between pivot
+    triangles of admissible clusters, symmetric to rounding, so G's far field
+    is stored once per pair (half the coupling entries, ranks above 64
+    included) and G x, G^T x equal the products from the full panels to
+    rounding."""
+    h = _lib()
+    v, t = synth.perturbed_sphere(16, seed=5)
+    kw = dict(kernel="slp", leaf=16, order_m=4, q_near=4, gca_tol=1e-8)
+    a = h.Operator(v, t, symmetric_near=True, **kw)
+    b = h.Operator(v, t, symmetric_near=False, **kw)
+    ia, ib = a.info(), b.info()
+    assert ia["max_rank_row"] > 64
+    assert ib["cpl_sym_entries"] == 0 and 2 * ia["cpl_sym_entries"] == ia["coupling_entries"]
+    for trans in (False, True):
+        x = synth.random_vector(len(t), 81 + trans)
+        ya, yb = _product(a, x, trans), _product(b, x, trans)
+        assert float(np.max(np.abs(ya - yb)) / np.max(np.abs(yb))) <= 1e-13, trans
+
+
 @pytest.mark.parametrize("m,eps", [(2, 1e-2), (3, 1e-4)])
 def test_gca_double_layer_matches_oracle_gca(m, eps):
     """K: triangle rows with the bases of G, vertex columns from the normal

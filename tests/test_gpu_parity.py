@@ -374,14 +374,15 @@ def test_once_per_pair_nearfield_matches_full(far_disabled, tol):
 
 
 @pytest.mark.parametrize("order,tol,dtype", [(3, 0.0, "f64"), (4, 0.0, "f64"), (4, 1e-6, "f64"),
-                                             (4, 1e-6, "f32")])
+                                             (4, 1e-6, "f32"), (5, 0.0, "f64")])
 def test_once_per_pair_coupling_matches_full(order, tol, dtype):
     """G x and G^T x with the far field stored once per pair of clusters
     (S_ts for s > t, S_st taken as its transpose) equal the products from the
     full coupling panels to rounding (FP64), or to FP32 summation-order error
     for an FP32 far field.  The stored pairs hold exactly half the coupling
     entries (blocks (t, s) and (s, t) have the same shape); with order 4
-    (rank 64) the panels are wider than one 256-column pass."""
+    (rank 64) the panels are wider than one 256-column pass, and order 5
+    (rank 125) has more rows than a wave has lanes."""
     h = _lib()
     v, t = synth.octa_sphere(16)
     kw = dict(kernel="slp", leaf=16, order_m=order, q_near=4, recompress_tol=tol, farfield_dtype=dtype)
@@ -399,13 +400,13 @@ def test_once_per_pair_coupling_matches_full(order, tol, dtype):
 
 
 def test_once_per_pair_coupling_only_where_it_applies():
-    """Ranks above 64, the Green cross approximation and BF16 couplings (on
-    recompressed bases) keep the full coupling panels; the double-layer
-    operator has no such storage."""
+    """BF16 couplings (on recompressed bases) and evaluated couplings keep
+    the full coupling panels or none; the double-layer operator has no such
+    storage."""
     h = _lib()
     v, t = synth.octa_sphere(8)
-    for kw in (dict(kernel="slp", order_m=5), dict(kernel="slp", order_m=3, farfield_dtype="bf16", recompress_tol=1e-6),
-               dict(kernel="slp", order_m=3, gca_tol=1e-4), dict(kernel="dlp", order_m=3)):
+    for kw in (dict(kernel="slp", order_m=3, farfield_dtype="bf16", recompress_tol=1e-6),
+               dict(kernel="slp", order_m=3, recompute_coupling=True), dict(kernel="dlp", order_m=3)):
         op = h.Operator(v, t, leaf=16, q_near=4, **kw)
         assert op.info()["cpl_sym_entries"] == 0, kw
 
