@@ -178,7 +178,12 @@ typedef struct {
     int order_m;            /* Chebyshev points per axis, k = m^3 per cluster; 1..6 */
     int q_near;             /* Gauss points per dimension of the near-field quadrature; 2..16 */
     double recompress_tol;  /* > 0: algebraic recompression of the cluster bases to this
-                               relative tolerance; 0: plain interpolation */
+                               relative tolerance (Section 5): orthogonalise the nested bases,
+                               weight each cluster by its farfield blocks and its ancestors',
+                               truncate, project the couplings; applies to the interpolation and
+                               to the gca_tol bases.  Ranks above 64 (order_m 5-6, cross
+                               approximation) need an FP64 far field (H2B_ENOTSUP otherwise);
+                               0: the bases as built */
     h2b_dtype farfield_dtype; /* storage/arithmetic of bases and coupling matrices */
     int transposed_copy;    /* 1: also store the nearfield and coupling matrices transposed and
                                grouped by column cluster, so that A^T x streams rows like A x
@@ -202,8 +207,9 @@ typedef struct {
                                interpolation and couplings A|_{t_hat x s_hat} from the nearfield
                                quadrature; bases built on the host.  For K the vertex clusters use
                                the normal derivative in y of Green's formula (Section 5).  G must
-                               be on one tree (H2B_ENOTSUP otherwise); excludes recompress_tol
-                               (H2B_EINVAL); 0 (default): interpolation */
+                               be on one tree (H2B_ENOTSUP otherwise); with recompress_tol > 0 the
+                               cross-approximation bases are recompressed (FP64 far field only);
+                               0 (default): interpolation */
     int recompute_coupling; /* 1: store no coupling matrices; every product evaluates
                                S_ts = g(xi_t, xi_s) at the interpolation points again (Section 2,
                                eq. (vsw); Section 3), trading their storage (the largest stored

@@ -6,28 +6,46 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
+#include <exception>
+#include <mutex>
 #include <thread>
 #include <vector>
 
 namespace h2b {
 
-// Runs f(i) for i in [0, n) on up to hardware_concurrency() threads.
+// Runs f(i) for i in [0, n) on up to hardware_concurrency() threads (at most
+// OMP_NUM_THREADS when that is set, and 64).  An exception thrown by f stops
+// the remaining work and is rethrown on the calling thread.
 template <class F> void parallel_for(int64_t n, F f)
 {
     if (n <= 0) return;
     int nt = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 64);
+    if (const char *e = std::getenv("OMP_NUM_THREADS")) {
+        const int lim = std::atoi(e);
+        if (lim > 0) nt = std::min(nt, lim);
+    }
     nt = (int)std::min<int64_t>(nt, n);
     if (nt <= 1) {
         for (int64_t i = 0; i < n; ++i) f(i);
         return;
     }
     std::atomic<int64_t> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
     std::vector<std::thread> th;
     for (int k = 0; k < nt; ++k)
         th.emplace_back([&] {
-            for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+            try {
+                for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+                next.store(n);
+            }
         });
     for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
 }
 
 // C (m x n) = A (m x k) * B (k x n)

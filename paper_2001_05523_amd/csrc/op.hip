@@ -263,11 +263,14 @@ std::unique_ptr<Op> assemble_op(std::shared_ptr<const Blocks> blocks, h2b_kernel
     if (kernel == H2B_DLP && blocks->cols->space != H2B_P1)
         fail(H2B_EINVAL, "the double-layer matrix needs a P1 column tree");
     if (kernel != H2B_SLP && kernel != H2B_DLP) fail(H2B_EINVAL, "unknown kernel");
-    if (p.recompress_tol > 0.0 && p.order_m > 4)
-        fail(H2B_ENOTSUP, "recompression supports order_m <= 4");
+    // ranks above 64 (orders 5-6, cross-approximation bases) are recompressed
+    // in FP64 only
+    if (p.recompress_tol > 0.0 && p.order_m > 4 && p.farfield_dtype != H2B_F64)
+        fail(H2B_ENOTSUP, "an FP32 or BF16 far field with recompression supports order_m <= 4");
     if (!(p.gca_tol >= 0.0) || !std::isfinite(p.gca_tol)) fail(H2B_EINVAL, "gca_tol must be finite and >= 0");
     const bool gca = p.gca_tol > 0.0;
-    if (gca && p.recompress_tol > 0.0) fail(H2B_EINVAL, "choose either recompression or the Green cross approximation");
+    if (gca && p.recompress_tol > 0.0 && p.farfield_dtype != H2B_F64)
+        fail(H2B_ENOTSUP, "the Green cross approximation is recompressed in FP64 only");
     if (kernel == H2B_SLP && blocks->rows != blocks->cols)
         fail(H2B_EINVAL, "the single-layer matrix needs one cluster tree for its rows and columns");
     // Reduced-precision storage keeps the error of the far field at the level

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "linalg.hpp"
 #include "op.hpp"
@@ -142,32 +143,151 @@ __global__ __launch_bounds__(NT) void k_gram_cols(ColPanelDev d, const double *_
     }
 }
 
+// ------------------------------------------------ ranks above RK
+//
+// The same three products for blocks with a dimension above RK (orders 5-6,
+// cross-approximation bases): tiles of RK x RK held in LDS, accumulators in
+// registers per tile, one workgroup per (block, output tile).
+
+constexpr int GT = 32;  // rows (sandwich) or columns (Gram) staged per step
+
+// out = L * In * R^T, FP64 output, for one output tile of RK x RK of one block
+// per workgroup: U = In[j0:j0+GT, :] R^T[:, tile] is staged in LDS for GT rows
+// of In at a time, then out[tile] += L[tile, j0:j0+GT] U.
+__global__ __launch_bounds__(NT) void k_sandwich_tiled(SandwichDev d, int tiles, const double *__restrict__ in,
+                                                       double *__restrict__ out, const double *__restrict__ L,
+                                                       const int64_t *__restrict__ Loff,
+                                                       const double *__restrict__ R,
+                                                       const int64_t *__restrict__ Roff)
+{
+    __shared__ double U[GT][RK + 1];
+    __shared__ double Lc[RK][GT + 1];
+    const int b = blockIdx.x / (tiles * tiles), tile = blockIdx.x % (tiles * tiles);
+    const int ai = d.a_in[b], bi = d.b_in[b], ao = d.a_out[b], bo = d.b_out[b];
+    const int i0 = (tile / tiles) * RK, c0 = (tile % tiles) * RK;
+    if (i0 >= ao || c0 >= bo) return;  // uniform over the workgroup
+    const int64_t io = d.in_off[b], oo = d.out_off[b];
+    const int is = d.in_stride[b], os = d.out_stride[b];
+    const double *Lt = L + Loff[d.t[b]];
+    const double *Rs = R + Roff[d.s[b]];
+    double acc[RK * RK / NT];
+    for (int k = 0; k < RK * RK / NT; ++k) acc[k] = 0.0;
+    for (int j0 = 0; j0 < ai; j0 += GT) {
+        // U[jj][c] = sum_l In[j0 + jj][l] R[c0 + c][l]
+        for (int e = threadIdx.x; e < GT * RK; e += NT) {
+            const int jj = e / RK, c = e % RK;
+            double sum = 0.0;
+            if (j0 + jj < ai && c0 + c < bo) {
+                const double *x = in + io + (int64_t)(j0 + jj) * is;
+                const double *r = Rs + (int64_t)(c0 + c) * bi;
+                for (int l = 0; l < bi; ++l) sum += x[l] * r[l];
+            }
+            U[jj][c] = sum;
+        }
+        for (int e = threadIdx.x; e < RK * GT; e += NT) {
+            const int i = e / GT, jj = e % GT;
+            Lc[i][jj] = (i0 + i < ao && j0 + jj < ai) ? Lt[(int64_t)(i0 + i) * ai + j0 + jj] : 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < RK * RK / NT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            const int i = e / RK, c = e % RK;
+            double sum = 0.0;
+            for (int jj = 0; jj < GT; ++jj) sum += Lc[i][jj] * U[jj][c];
+            acc[k] += sum;
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < RK * RK / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int i = e / RK, c = e % RK;
+        if (i0 + i < ao && c0 + c < bo) out[oo + (int64_t)(i0 + i) * os + c0 + c] = acc[k];
+    }
+}
+
+// Gram of each row panel, Z = P P^T, one RK x RK tile (i0, j0) per workgroup.
+__global__ __launch_bounds__(NT) void k_gram_rows_tiled(RowPanelDev d, int tiles, const double *__restrict__ vals,
+                                                        double *__restrict__ gram,
+                                                        const int64_t *__restrict__ goff)
+{
+    __shared__ double Ci[RK][GT + 1], Cj[RK][GT + 1];
+    const int g = blockIdx.x / (tiles * tiles), tile = blockIdx.x % (tiles * tiles);
+    const int a = d.nrows[g], nc = d.ncols[g];
+    const int i0 = (tile / tiles) * RK, j0 = (tile % tiles) * RK;
+    if (i0 >= a || j0 >= a) return;  // uniform over the workgroup
+    const int64_t off = d.val_off[g];
+    double acc[RK * RK / NT];
+    for (int k = 0; k < RK * RK / NT; ++k) acc[k] = 0.0;
+    for (int c0 = 0; c0 < nc; c0 += GT) {
+        for (int e = threadIdx.x; e < RK * GT; e += NT) {
+            const int r = e / GT, c = e % GT;
+            const bool in = c0 + c < nc;
+            Ci[r][c] = (in && i0 + r < a) ? vals[off + (int64_t)(i0 + r) * nc + c0 + c] : 0.0;
+            Cj[r][c] = (in && j0 + r < a) ? vals[off + (int64_t)(j0 + r) * nc + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < RK * RK / NT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            const int i = e / RK, j = e % RK;
+            double sum = 0.0;
+            for (int c = 0; c < GT; ++c) sum += Ci[i][c] * Cj[j][c];
+            acc[k] += sum;
+        }
+        __syncthreads();
+    }
+    double *G = gram + goff[d.tag[g]];
+    for (int k = 0; k < RK * RK / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int i = e / RK, j = e % RK;
+        if (i0 + i < a && j0 + j < a) G[(int64_t)(i0 + i) * a + j0 + j] = acc[k];
+    }
+}
+
+// Gram of each column group, Z = sum over blocks of B^T B, one RK x RK tile
+// (i0, j0) per workgroup.
+__global__ __launch_bounds__(NT) void k_gram_cols_tiled(ColPanelDev d, int tiles, const double *__restrict__ vals,
+                                                        double *__restrict__ gram,
+                                                        const int64_t *__restrict__ goff,
+                                                        const int32_t *__restrict__ gtag)
+{
+    __shared__ double Ci[GT][RK + 1], Cj[GT][RK + 1];
+    const int g = blockIdx.x / (tiles * tiles), tile = blockIdx.x % (tiles * tiles);
+    const int b = d.out_len[g];
+    const int i0 = (tile / tiles) * RK, j0 = (tile % tiles) * RK;
+    if (i0 >= b || j0 >= b) return;  // uniform over the workgroup
+    double acc[RK * RK / NT];
+    for (int k = 0; k < RK * RK / NT; ++k) acc[k] = 0.0;
+    for (int blk = d.blk_ptr[g]; blk < d.blk_ptr[g + 1]; ++blk) {
+        const int nr = d.b_nrows[blk];
+        const int64_t stride = d.b_stride[blk];
+        const double *base = vals + d.b_val_off[blk] + d.b_c0[blk];
+        for (int r0 = 0; r0 < nr; r0 += GT) {
+            for (int e = threadIdx.x; e < GT * RK; e += NT) {
+                const int r = e / RK, j = e % RK;
+                const bool in = r0 + r < nr;
+                Ci[r][j] = (in && i0 + j < b) ? base[(int64_t)(r0 + r) * stride + i0 + j] : 0.0;
+                Cj[r][j] = (in && j0 + j < b) ? base[(int64_t)(r0 + r) * stride + j0 + j] : 0.0;
+            }
+            __syncthreads();
+            for (int k = 0; k < RK * RK / NT; ++k) {
+                const int e = threadIdx.x + k * NT;
+                const int i = e / RK, j = e % RK;
+                double sum = 0.0;
+                for (int r = 0; r < GT; ++r) sum += Ci[r][i] * Cj[r][j];
+                acc[k] += sum;
+            }
+            __syncthreads();
+        }
+    }
+    double *G = gram + goff[gtag[g]];
+    for (int k = 0; k < RK * RK / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int i = e / RK, j = e % RK;
+        if (i0 + i < b && j0 + j < b) G[(int64_t)(i0 + i) * b + j0 + j] = acc[k];
+    }
+}
+
 // ----------------------------------------------------------------- host
-
-// One-dimensional Lagrange polynomial ell_a on the m points pts, at z.
-double lag1_host(const double *pts, int m, int a, double z)
-{
-    double v = 1.0;
-    for (int b = 0; b < m; ++b)
-        if (b != a) v *= (z - pts[b]) / (pts[a] - pts[b]);
-    return v;
-}
-
-// Interpolation transfer of child c into its parent t, (E_c)_{mu nu} =
-// L_{t,nu}(xi_{c,mu}), k x k row-major.
-void cheb_transfer(const double *axt, const double *axc, int m, std::vector<double> &E)
-{
-    const int k = m * m * m;
-    double e[3][8][8];
-    for (int d = 0; d < 3; ++d)
-        for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) e[d][a][b] = lag1_host(axt + d * m, m, b, axc[d * m + a]);
-    E.resize((size_t)k * k);
-    for (int mu = 0; mu < k; ++mu)
-        for (int nu = 0; nu < k; ++nu)
-            E[(size_t)mu * k + nu] = e[0][mu % m][nu % m] * e[1][(mu / m) % m][(nu / m) % m] *
-                                     e[2][mu / (m * m)][nu / (m * m)];
-}
 
 // Orthogonalised cluster basis: V_t = Q_t R_t, Q_parent|_c = Q_c F_c.
 struct Ortho {
@@ -183,46 +303,75 @@ struct Ortho {
     std::vector<std::vector<double>> newtr;    // parents: k'_t x (k'_c0 + k'_c1)
 };
 
-void orthogonalise(const Basis &B, int m, const std::vector<double> &leafT, Ortho &o)
+// V_t = Q_t R_t bottom-up from the stored basis values: a leaf's V_t is its
+// stored panel transposed (|t| x k_t); a parent's is [V_c0 E_c0; V_c1 E_c1]
+// with E_c (k_c x k_t) read from its stored transfer panel [E_c0^T | E_c1^T],
+// so Q_t restricted to child c is Q_c F_c with [F_c0; F_c1] R_t the QR of
+// [R_c0 E_c0; R_c1 E_c1].  Works for any per-cluster ranks (interpolation
+// k = m^3, or the cross approximation's).
+void orthogonalise(const Basis &B, const std::vector<double> &leafT, const std::vector<double> &trT, Ortho &o)
 {
     const Tree &T = *B.tree;
     const int64_t nc = T.nclusters();
-    const int k = m * m * m;
     o.r.assign(nc, 0);
     o.R.assign(nc, {});
     o.Q.assign(nc, {});
     o.F.assign(nc, {});
-    std::vector<double> axes((size_t)nc * 3 * m);
-    for (int64_t c = 0; c < nc; ++c) cheb_axes(T, (int)c, m, &axes[(size_t)c * 3 * m]);
-    std::vector<int64_t> leaf_off(nc, -1);
-    for (int g = 0; g < B.leaf.ngroups(); ++g) leaf_off[B.leaf.group_tag[g]] = B.leaf.val_off[g];
+    std::vector<int> leaf_g(nc, -1), tr_g(nc, -1);
+    for (int g = 0; g < B.leaf.ngroups(); ++g) leaf_g[B.leaf.group_tag[g]] = g;
+    for (int g = 0; g < B.trans.ngroups(); ++g) tr_g[B.trans.group_tag[g]] = g;
     for (int lev = T.nlevels - 1; lev >= 0; --lev) {
         const auto &cl = T.by_level[lev];
         parallel_for((int64_t)cl.size(), [&](int64_t idx) {
             const int c = cl[idx];
+            const int kc = B.rank[c];
             if (T.nchild[c] == 0) {
                 const int n = T.size(c);
-                std::vector<double> V((size_t)n * k);
-                const double *src = &leafT[leaf_off[c]];  // k x n
-                for (int nu = 0; nu < k; ++nu)
-                    for (int i = 0; i < n; ++i) V[(size_t)i * k + nu] = src[(size_t)nu * n + i];
-                householder_qr(n, k, V.data(), o.Q[c], o.R[c]);
-                o.r[c] = std::min(n, k);
-            } else {
-                const int c0 = T.child0[c], c1 = T.child1[c];
-                const int r0 = o.r[c0], r1 = o.r[c1];
-                std::vector<double> W((size_t)(r0 + r1) * k), E;
-                cheb_transfer(&axes[(size_t)c * 3 * m], &axes[(size_t)c0 * 3 * m], m, E);
-                gemm_nn(r0, k, k, o.R[c0].data(), E.data(), W.data());
-                cheb_transfer(&axes[(size_t)c * 3 * m], &axes[(size_t)c1 * 3 * m], m, E);
-                gemm_nn(r1, k, k, o.R[c1].data(), E.data(), W.data() + (size_t)r0 * k);
-                std::vector<double> Qh;
-                householder_qr(r0 + r1, k, W.data(), Qh, o.R[c]);
-                const int rc = std::min(r0 + r1, k);
-                o.r[c] = rc;
-                o.F[c0].assign(Qh.begin(), Qh.begin() + (size_t)r0 * rc);
-                o.F[c1].assign(Qh.begin() + (size_t)r0 * rc, Qh.end());
+                const int g = leaf_g[c];
+                if (kc == 0 || n == 0 || g < 0) return;  // rank 0
+                if (B.leaf.nrows[g] != kc || B.leaf.ncols[g] != n) fail(H2B_EDEVICE, "leaf panel of unexpected shape");
+                std::vector<double> V((size_t)n * kc);
+                const double *src = &leafT[B.leaf.val_off[g]];  // kc x n
+                for (int nu = 0; nu < kc; ++nu)
+                    for (int i = 0; i < n; ++i) V[(size_t)i * kc + nu] = src[(size_t)nu * n + i];
+                householder_qr(n, kc, V.data(), o.Q[c], o.R[c]);
+                o.r[c] = std::min(n, kc);
+                return;
             }
+            const int ch[2] = {T.child0[c], T.child1[c]};
+            const int r0 = o.r[ch[0]], r1 = o.r[ch[1]];
+            const int g = tr_g[c];
+            if (kc == 0 || r0 + r1 == 0 || g < 0) {  // rank 0: the children's F have no columns
+                o.F[ch[0]].clear();
+                o.F[ch[1]].clear();
+                return;
+            }
+            if (B.trans.nrows[g] != kc) fail(H2B_EDEVICE, "transfer panel of unexpected shape");
+            const int ncol = B.trans.ncols[g];
+            const double *P = &trT[B.trans.val_off[g]];  // kc x ncol
+            std::vector<double> W((size_t)(r0 + r1) * kc, 0.0);
+            int roff = 0;
+            for (int q = 0; q < 2; ++q) {
+                const int cc = ch[q], rq = o.r[cc], kq = B.rank[cc];
+                if (rq > 0) {
+                    int seg = -1;
+                    for (int j = B.trans.seg_ptr[g]; j < B.trans.seg_ptr[g + 1]; ++j)
+                        if (B.trans.seg_tag[j] == cc) seg = j;
+                    if (seg < 0 || B.trans.seg_len[seg] != kq) fail(H2B_EDEVICE, "transfer segment of unexpected shape");
+                    const int s0 = B.trans.seg_c0[seg];
+                    std::vector<double> E((size_t)kq * kc);  // E[mu][nu] = P[nu][s0 + mu]
+                    for (int mu = 0; mu < kq; ++mu)
+                        for (int nu = 0; nu < kc; ++nu) E[(size_t)mu * kc + nu] = P[(size_t)nu * ncol + s0 + mu];
+                    gemm_nn(rq, kc, kq, o.R[cc].data(), E.data(), W.data() + (size_t)roff * kc);
+                }
+                roff += rq;
+            }
+            std::vector<double> Qh;
+            householder_qr(r0 + r1, kc, W.data(), Qh, o.R[c]);
+            const int rc = std::min(r0 + r1, kc);
+            o.r[c] = rc;
+            o.F[ch[0]].assign(Qh.begin(), Qh.begin() + (size_t)r0 * rc);
+            o.F[ch[1]].assign(Qh.begin() + (size_t)r0 * rc, Qh.end());
         });
     }
 }
@@ -424,6 +573,21 @@ void run_sandwich(Sandwich &sw, const double *in, TO *out, const DevMem &L, cons
     if (sw.t.empty()) return;
     sw.upload(st);
     const int64_t n = (int64_t)sw.t.size();
+    int big = 0;
+    for (int64_t b = 0; b < n; ++b)
+        big = std::max({big, sw.a_in[b], sw.b_in[b], sw.a_out[b], sw.b_out[b]});
+    if (big > RK) {
+        if (!std::is_same<TO, double>::value)
+            fail(H2B_ENOTSUP, "recompression of ranks above 64 needs an FP64 far field");
+        const int tiles = (std::max(*std::max_element(sw.a_out.begin(), sw.a_out.end()),
+                                    *std::max_element(sw.b_out.begin(), sw.b_out.end())) + RK - 1) / RK;
+        if (n * tiles * tiles >= (int64_t)1 << 31) fail(H2B_ENOTSUP, "too many coupling blocks for one launch");
+        hipLaunchKernelGGL(k_sandwich_tiled, dim3((unsigned)(n * tiles * tiles)), dim3(NT), 0, st, sw.dev, tiles, in,
+                           reinterpret_cast<double *>(out), L.as<double>(), Loff.as<int64_t>(), R.as<double>(),
+                           Roff.as<int64_t>());
+        hip_check(hipGetLastError(), "sandwich launch");
+        return;
+    }
     for (int64_t b0 = 0; b0 < n; b0 += (1 << 30)) {
         // one launch covers every block (n < 2^31 blocks)
         hipLaunchKernelGGL(k_sandwich<TO>, dim3((unsigned)std::min<int64_t>(n - b0, 1 << 30)), dim3(NT), 0,
@@ -469,20 +633,21 @@ void recompress_op(Op &op, double tol, hipStream_t st)
 {
     const int m = op.params.order_m;
     const int k = m * m * m;
-    if (k > RK) fail(H2B_ENOTSUP, "recompression supports order_m <= 4");
     const bool shared = (op.colb == op.rowb);
     std::vector<Basis *> bases{op.rowb.get()};
     if (!shared) bases.push_back(op.colb.get());
     std::vector<Ortho> orth(bases.size());
 
-    // 1. orthogonalise (leaf bases from the device)
+    // 1. orthogonalise (leaf and transfer values from the device)
     for (size_t bi = 0; bi < bases.size(); ++bi) {
         Basis &B = *bases[bi];
-        std::vector<double> leafT(std::max<int64_t>(B.leaf.total, 1));
-        hip_check(hipMemcpy(leafT.data(), B.leaf_vals.p, sizeof(double) * B.leaf.total,
-                            hipMemcpyDeviceToHost),
+        std::vector<double> leafT(std::max<int64_t>(B.leaf.total, 1)), trT(std::max<int64_t>(B.trans.total, 1));
+        hip_check(hipMemcpy(leafT.data(), B.leaf_vals.p, sizeof(double) * B.leaf.total, hipMemcpyDeviceToHost),
                   "leaf download");
-        orthogonalise(B, m, leafT, orth[bi]);
+        if (B.trans.total > 0)
+            hip_check(hipMemcpy(trT.data(), B.trans_vals.p, sizeof(double) * B.trans.total, hipMemcpyDeviceToHost),
+                      "transfer download");
+        orthogonalise(B, leafT, trT, orth[bi]);
     }
     Ortho &orow = orth[0];
     Ortho &ocol = shared ? orth[0] : orth[1];
@@ -540,11 +705,22 @@ void recompress_op(Op &op, double tol, hipStream_t st)
     hip_check(hipMemcpyAsync(dtag.p, ctag.data(), sizeof(int32_t) * ctag.size(), hipMemcpyHostToDevice, st),
               "upload");
     if (cplO.ngroups() > 0) {
-        hipLaunchKernelGGL(k_gram_rows, dim3(cplO.ngroups()), dim3(NT), 0, st, cplO.dev, stil.as<double>(),
-                           dgr.as<double>(), dgro.as<int64_t>());
+        const int tr = (cplO.max_nrows + RK - 1) / RK, tc = (cplOT.max_out + RK - 1) / RK;
+        if ((int64_t)cplO.ngroups() * tr * tr >= (int64_t)1 << 31 || (int64_t)cplOT.ngroups() * tc * tc >= (int64_t)1 << 31)
+            fail(H2B_ENOTSUP, "too many coupling groups for one launch");
+        if (tr <= 1)
+            hipLaunchKernelGGL(k_gram_rows, dim3(cplO.ngroups()), dim3(NT), 0, st, cplO.dev, stil.as<double>(),
+                               dgr.as<double>(), dgro.as<int64_t>());
+        else
+            hipLaunchKernelGGL(k_gram_rows_tiled, dim3(cplO.ngroups() * tr * tr), dim3(NT), 0, st, cplO.dev, tr,
+                               stil.as<double>(), dgr.as<double>(), dgro.as<int64_t>());
         hip_check(hipGetLastError(), "gram launch");
-        hipLaunchKernelGGL(k_gram_cols, dim3(cplOT.ngroups()), dim3(NT), 0, st, cplOT.dev, stil.as<double>(),
-                           dgc.as<double>(), dgco.as<int64_t>(), dtag.as<int32_t>());
+        if (tc <= 1)
+            hipLaunchKernelGGL(k_gram_cols, dim3(cplOT.ngroups()), dim3(NT), 0, st, cplOT.dev, stil.as<double>(),
+                               dgc.as<double>(), dgco.as<int64_t>(), dtag.as<int32_t>());
+        else
+            hipLaunchKernelGGL(k_gram_cols_tiled, dim3(cplOT.ngroups() * tc * tc), dim3(NT), 0, st, cplOT.dev, tc,
+                               stil.as<double>(), dgc.as<double>(), dgco.as<int64_t>(), dtag.as<int32_t>());
         hip_check(hipGetLastError(), "gram launch");
     }
     std::vector<double> hgr(grow.back()), hgc(gcol.back());

@@ -76,6 +76,37 @@ def test_gca_once_per_pair_coupling_matches_full():
         assert float(np.max(np.abs(ya - yb)) / np.max(np.abs(yb))) <= 1e-13, trans
 
 
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_gca_recompressed_against_oracle_gca(kernel):
+    """Algebraic recompression (Section 5) of the cross-approximation bases,
+    whose ranks reach 176 here (the tiled sandwich and Gram kernels): the
+    products stay within a small multiple of the tolerance of the oracle's
+    dense GCA matrix, with fewer coefficients and coupling entries."""
+    torch = _torch()
+    h = _lib()
+    v, t = synth.perturbed_sphere(16, seed=5)
+    eps, tol = 1e-8, 1e-6
+    if kernel == "slp":
+        A, _ = gca.gca_dense(v, t, 16, 4, eps, oracle.slp_dense(v, t, 4))
+    else:
+        A, _ = gca.gca_dense_dlp(v, t, 16, 4, eps, oracle.dlp_dense(v, t, 4))
+    kw = dict(kernel=kernel, leaf=16, order_m=4, q_near=4, gca_tol=eps)
+    plain = h.Operator(v, t, **kw)
+    rc = h.Operator(v, t, recompress_tol=tol, **kw)
+    ip, ir = plain.info(), rc.info()
+    assert ip["max_rank_row"] > 64
+    assert ir["row_coeffs"] < ip["row_coeffs"] and ir["coupling_entries"] < ip["coupling_entries"]
+    for trans in (False, True):
+        x = synth.random_vector(A.shape[0] if trans else A.shape[1], 91 + trans)
+        X = torch.tensor(x, device="cuda")
+        y = ((rc.T if trans else rc) @ X).cpu().numpy()
+        ref = (A.T if trans else A) @ x
+        err = _rel(y, ref)
+        print("%s trans=%d recompressed GCA vs oracle GCA: %.3e, coefficients %d -> %d"
+              % (kernel, trans, err, ip["row_coeffs"], ir["row_coeffs"]))
+        assert err <= 20 * tol
+
+
 @pytest.mark.parametrize("m,eps", [(2, 1e-2), (3, 1e-4)])
 def test_gca_double_layer_matches_oracle_gca(m, eps):
     """K: triangle rows with the bases of G, vertex columns from the normal
@@ -125,8 +156,8 @@ def test_gca_error_falls_with_the_tolerance():
 
 def test_gca_mixed_precision_and_arguments():
     """The cross-approximation bases are not orthonormal, so an FP32 or BF16
-    far field on them is refused (H2B_ENOTSUP); GCA together with
-    recompression is refused as a contradictory request (H2B_EINVAL)."""
+    far field on them is refused (H2B_ENOTSUP), and so is their
+    recompression into FP32 storage (FP64 only)."""
     h = _lib()
     v, t = synth.octa_sphere(16)
     for kernel in ("slp", "dlp"):
@@ -135,8 +166,9 @@ def test_gca_mixed_precision_and_arguments():
                 h.Operator(v, t, kernel=kernel, leaf=32, order_m=4, q_near=4, gca_tol=1e-6, farfield_dtype=dt)
             assert e.value.code == h.H2B_ENOTSUP
     with pytest.raises(h.H2BError) as e:
-        h.Operator(v, t, kernel="slp", leaf=32, order_m=3, q_near=4, gca_tol=1e-4, recompress_tol=1e-6)
-    assert e.value.code == h.H2B_EINVAL
+        h.Operator(v, t, kernel="slp", leaf=32, order_m=3, q_near=4, gca_tol=1e-4, recompress_tol=1e-6,
+                   farfield_dtype="f32")
+    assert e.value.code == h.H2B_ENOTSUP
 
 
 def test_gca_operator_refuses_shape_derivatives():

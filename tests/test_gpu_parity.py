@@ -209,6 +209,31 @@ def test_recompressed_against_oracle_h2(kernel, s, leaf):
         assert err <= 20 * tol
 
 
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_recompressed_order5_against_oracle_h2(kernel):
+    """Recompression of order-5 interpolation bases (k = 125 > 64: the tiled
+    sandwich and Gram kernels and the orthogonalisation from the stored
+    transfer matrices): within a small multiple of the tolerance of the
+    oracle's (uncompressed) H^2 matrix, with lower ranks."""
+    h = _lib()
+    s, q, m, tol, leaf = 16, 4, 5, 1e-6, 16
+    v, t = synth.octa_sphere(s)
+    op = h.Operator(v, t, kernel=kernel, leaf=leaf, order_m=m, q_near=q, recompress_tol=tol)
+    info = op.info()
+    assert info["max_rank_row"] < m ** 3 and info["mean_rank_row"] < 64
+    A = _dense(s, kernel, q)
+    H, _ = h2.h2_dense(v, t, kernel, leaf, m, near_matrix=A)
+    for trans in (False, True):
+        nin = A.shape[0] if trans else A.shape[1]
+        x = synth.random_vector(nin, 25 + trans)
+        y = _run(op, x, trans=trans)
+        Hx = (H.T if trans else H) @ x
+        err = np.linalg.norm(y - Hx) / np.linalg.norm(Hx)
+        print("%s trans=%d order-5 recompressed vs oracle H2: %.3e, mean rank %.1f, max %d"
+              % (kernel, trans, err, info["mean_rank_row"], info["max_rank_row"]))
+        assert err <= 20 * tol
+
+
 def test_recompressed_mixed_precision():
     """FP32 storage of the recompressed (orthonormal) bases and couplings stays
     within 1e-5 of the FP64 recompressed product."""

@@ -131,8 +131,8 @@ def test_assembly_arguments_rejected_on_the_host():
     """Requests that assembly refuses before any device call: the
     single-layer matrix on two different triangle trees (its column basis is
     the row basis), an FP32 or BF16 far field on non-orthonormal bases
-    (interpolation without recompression, cross approximation), parameters
-    out of range."""
+    (interpolation without recompression, cross approximation) or with
+    ranks above 64 recompressed into it, parameters out of range."""
     h = _lib()
     v, t = synth.octa_sphere(4)
     m = h.Mesh(v, t)
@@ -149,7 +149,11 @@ def test_assembly_arguments_rejected_on_the_host():
             assert _assemble_status(h, blk, ker, farfield_dtype=dt) == h.H2B_ENOTSUP
             assert _assemble_status(h, blk, ker, farfield_dtype=dt, gca_tol=1e-4) == h.H2B_ENOTSUP
             assert b"orthonormal" in h.h2b_last_error()
-    assert _assemble_status(h, B, h.H2B_SLP, gca_tol=1e-4, recompress_tol=1e-6) == h.H2B_EINVAL
+    # ranks above 64 (cross approximation, orders 5-6) are recompressed in FP64 only
+    assert _assemble_status(h, B, h.H2B_SLP, gca_tol=1e-4, recompress_tol=1e-6,
+                            farfield_dtype=h.H2B_F32) == h.H2B_ENOTSUP
+    assert _assemble_status(h, B, h.H2B_SLP, order_m=5, recompress_tol=1e-6,
+                            farfield_dtype=h.H2B_F32) == h.H2B_ENOTSUP
     assert _assemble_status(h, B, h.H2B_SLP, order_m=7) == h.H2B_EINVAL
     assert _assemble_status(h, B, h.H2B_SLP, q_near=1) == h.H2B_EINVAL
     assert _assemble_status(h, B, h.H2B_DLP) == h.H2B_EINVAL  # K needs a P1 column tree
