@@ -430,13 +430,15 @@ def hchol_solves(torch, h2b, sizes):
 
 def gca_solve(torch, h2b, mesh, verts, tris, args):
     """Dirichlet-to-Neumann solve with the Green cross approximation (order
-    args.gca_order per face direction, tolerance args.gca_tol) for both G and
-    K, no transposed copies (the solve uses G x and K x only): setup, storage,
-    product time and the L2 error of the Neumann data of u1 = x1^2 - x3^2."""
-    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, GCA order %d tol %g, block-Jacobi PCG tol 1e-8"
-                      % (args.gca_order, args.gca_tol)}
+    args.gca_order per face direction, tolerance args.gca_tol, bases
+    recompressed to args.gca_recompress) for both G and K, no transposed
+    copies (the solve uses G x and K x only): setup, storage, product time,
+    the error on the stored oracle rows, and the L2 error of the Neumann data
+    of u1 = x1^2 - x3^2."""
+    res = {"problem": "G t = (M/2 + K) u, u = x1^2 - x3^2, GCA order %d tol %g recompressed to %g, "
+                      "block-Jacobi PCG tol 1e-8" % (args.gca_order, args.gca_tol, args.gca_recompress)}
     kw = dict(leaf=args.leaf, order_m=args.gca_order, q_near=args.q_near, gca_tol=args.gca_tol,
-              transposed_copy=False, mesh=mesh)
+              recompress_tol=args.gca_recompress, transposed_copy=False, mesh=mesh)
     gops = {}
     for name, kern in (("G", "slp"), ("K", "dlp")):
         t0 = time.perf_counter()
@@ -458,6 +460,23 @@ def gca_solve(torch, h2b, mesh, verts, tris, args):
         G.matvec(x, y)
     torch.cuda.synchronize()
     res["G"]["ms_Ax"] = round((time.perf_counter() - t0) * 1e3 / 5, 4)
+    log("GCA G x: %.3f ms" % res["G"]["ms_Ax"])
+    # the 1,000 oracle rows stored for this mesh, if present
+    gold_path = os.path.join(ROOT, "tests", "golden", "sphere2M_oracle_rows.json")
+    if os.path.exists(gold_path) and args.s == 512 and args.q_near == 6 and args.leaf == 64:
+        import synth
+        with open(gold_path) as fh:
+            gold = json.load(fh)
+        rows = np.asarray(gold["rows"])
+        acc = {}
+        for name in ("G", "K"):
+            n_in = len(tris) if name == "G" else len(verts)
+            xg = torch.tensor(synth.random_vector(n_in, gold[name]["x_seed"]), device="cuda")
+            got = (gops[name] @ xg).cpu().numpy()[rows]
+            ref = np.asarray(gold[name]["y"])
+            acc[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res["oracle_rows_1000"] = acc
+        log("GCA on the 1,000 stored oracle rows: G %.3e, K %.3e" % (acc["G"], acc["K"]))
     u = torch.tensor(verts[:, 0] ** 2 - verts[:, 2] ** 2, dtype=torch.float64, device="cuda")
     b = h2b.dtn_rhs(gops["K"], u)
     t = torch.zeros_like(b)
@@ -534,6 +553,8 @@ def main():
                     help="skip the solves with GCA operators (about a minute of setup)")
     ap.add_argument("--gca-order", type=int, default=4)
     ap.add_argument("--gca-tol", type=float, default=1e-6)
+    ap.add_argument("--gca-recompress", type=float, default=1e-6,
+                    help="recompression tolerance of the GCA bases (0: none)")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the Dirichlet-to-Neumann and Neumann-to-Dirichlet CG solves")
     ap.add_argument("--copy-calib", action="store_true",

@@ -120,9 +120,11 @@ def test_sphere_2M_1000_oracle_rows():
 @pytest.mark.skipif(not os.path.exists(GOLDEN_2M), reason="stored oracle rows not generated")
 def test_sphere_2M_gca_1000_oracle_rows():
     """The same 1,000 stored oracle rows against the Green cross
-    approximation of G and K (order 4 per face direction, tolerance 1e-6):
-    GCA reaches the accuracy that order-4 interpolation cannot (both within
-    1e-5, measured 1.4e-6, against 2.5e-4 and 2.0e-2)."""
+    approximation of G and K (order 4 per face direction, tolerance 1e-6), as
+    built and with its bases recompressed to 1e-6: GCA reaches the accuracy
+    that order-4 interpolation cannot (all within 1e-5; measured 1.4e-6 as
+    built and 3-4e-6 recompressed, against 2.5e-4 and 2.0e-2), and the
+    recompression shrinks its far field at least threefold."""
     import json
     import paper_2001_05523_amd as h2b
     with open(GOLDEN_2M) as fh:
@@ -133,10 +135,14 @@ def test_sphere_2M_gca_1000_oracle_rows():
     for name, kernel, bound in (("G", "slp", 1e-5), ("K", "dlp", 1e-5)):
         ref = np.asarray(gold[name]["y"])
         x = synth.random_vector(len(t) if kernel == "slp" else len(v), gold[name]["x_seed"])
-        op = h2b.Operator(mesh=mesh, kernel=kernel, leaf=64, order_m=4, q_near=gold["q_near"], gca_tol=1e-6,
-                          transposed_copy=False)
-        y = _product(op, x)
-        del op
-        err = _rel(y[rows], ref)
-        print(name, "GCA 1000-row error %.3e" % err)
-        assert err <= bound
+        far = {}
+        for rc in (0.0, 1e-6):
+            op = h2b.Operator(mesh=mesh, kernel=kernel, leaf=64, order_m=4, q_near=gold["q_near"], gca_tol=1e-6,
+                              recompress_tol=rc, transposed_copy=False)
+            y = _product(op, x)
+            far[rc] = op.info()["bytes_far"]
+            del op
+            err = _rel(y[rows], ref)
+            print(name, "GCA (recompressed to %g) 1000-row error %.3e, far field %.2f GB" % (rc, err, far[rc] / 1e9))
+            assert err <= bound
+        assert far[1e-6] * 3 <= far[0.0]
