@@ -32,13 +32,26 @@ KERNEL_SOURCES = ["kernels.hip", "symnear.hip", "symcpl.hip", "op.hip", "transfo
                   "device.hpp", "op.hpp"]
 
 
-def sources_digest():
-    """sha256 over the library sources that define the product kernels."""
+def code_text(src):
+    """The code of a C++/HIP source without its comments and blank lines (the
+    HBM traffic of a kernel depends on its code, not on its comments)."""
+    import re
+    src = re.sub(rb"/\*.*?\*/", b"", src, flags=re.S)
+    src = re.sub(rb"//[^\n]*", b"", src)
+    return b"\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
+def sources_digest(read=None):
+    """sha256 over the code of the library sources that define the product
+    kernels (read(name) -> bytes; default: the files in the tree)."""
     import hashlib
+    if read is None:
+        def read(f):
+            with open(os.path.join(ROOT, "paper_2001_05523_amd", "csrc", f), "rb") as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2001_05523_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(code_text(read(f)))
     return h.hexdigest()
 
 

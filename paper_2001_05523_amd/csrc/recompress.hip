@@ -6,8 +6,10 @@
 // The paper turns its cross-approximation matrices into H^2 form with the
 // algebraic compression of its reference [BO07a] (Section 3; Section 5 notes it
 // yields close to the best H^2 approximation); here the same idea is applied
-// to the interpolation H^2 matrix:
-//   1. V_t = Q_t R_t with Q_t orthonormal and nested (QR bottom-up);
+// to an H^2 matrix with nested bases, from interpolation or from the Green
+// cross approximation (any per-cluster ranks):
+//   1. V_t = Q_t R_t with Q_t orthonormal and nested (QR bottom-up, from the
+//      stored leaf and transfer matrices);
 //   2. S~_ts = R_t S_ts R'_s^T (GPU);
 //   3. Gram weights Z_t = sum_s S~_ts S~_ts^T + F_t Z_parent F_t^T (GPU sums,
 //      host recursion top-down);
@@ -27,7 +29,7 @@ namespace h2b {
 
 namespace {
 
-constexpr int RK = 64;  // largest rank handled by the recompression kernels
+constexpr int RK = 64;  // tile of the recompression kernels (larger blocks: the tiled kernels)
 constexpr int NT = 256;
 
 struct SandwichDev {

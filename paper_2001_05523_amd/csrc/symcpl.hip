@@ -1,8 +1,12 @@
 // Far field of G stored once per pair of clusters.
 //
 // G's kernel is symmetric and G uses one cluster basis for rows and columns,
-// so its coupling matrices satisfy S_st = S_ts^T (Section 2, eq. (vsw): both
-// are g evaluated at the same pairs of interpolation points).  For every row
+// so its coupling matrices satisfy S_st = S_ts^T: with interpolation both are
+// g at the same pairs of interpolation points (Section 2, eq. (vsw)); with the
+// cross approximation both hold G's entries between the same pivot triangles
+// of two admissible clusters (Section 4), whose quadrature sums the same
+// terms; after recompression both are projected onto the same bases, so the
+// equality holds to rounding.  For every row
 // cluster t the panel [S_ts for the farfield clusters s > t] is stored; one
 // pass (k_cplsym) reads each block once for the row sums y^_t += S_ts x^_s
 // and the column sums S_ts^T x^_t, which go to a scratch vector, and a
@@ -33,8 +37,8 @@ template <typename T> __device__ inline T wave_sum_c(T v)
     return v;
 }
 
-// One wave per stored row cluster t (rank at most SYMCPL_MAX_RANK).  A pass covers 256
-// panel columns, one per lane and column block; the inputs x^_s of its columns
+// One wave per stored row cluster t (rank at most SYMCPL_MAX_RANK).  A pass
+// covers 256 panel columns, one per lane and column block; the inputs x^_s of its columns
 // are gathered once (segment by binary search) and the column sums stay in
 // registers.  Each step loads 4 rows of the pass (4 x 4 non-temporal loads in
 // flight; blocks past the panel's end are skipped for the whole wave, the

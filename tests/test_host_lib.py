@@ -235,3 +235,27 @@ def test_bench_runs_on_one_gpu_only():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_traffic_record_keyed_by_kernel_code():
+    """The counter traffic in profiles/traffic.json is used only for the code
+    it was measured on: the digest ignores comments and blank lines, changes
+    with any code token, and matches the kernel sources in the tree."""
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = b"int f(int a) { // add one\n  return a + 1; /* the\n  result */\n}\n\n"
+    same = b"int f(int a) {\n\n  return a + 1;\n}\n"
+    other = b"int f(int a) {\n  return a + 2;\n}\n"
+    assert bench.code_text(src) == bench.code_text(same)
+    assert bench.code_text(src) != bench.code_text(other)
+    files = {"kernels.hip": src}
+    read = lambda f: files.get(f, b"")
+    d1 = bench.sources_digest(read)
+    files["kernels.hip"] = same
+    assert bench.sources_digest(read) == d1
+    files["kernels.hip"] = other
+    assert bench.sources_digest(read) != d1
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        assert json.load(fh)["sources_sha256"] == bench.sources_digest()
