@@ -369,6 +369,130 @@ __global__ __launch_bounds__(NT) void k_panel_mfma(RowPanelDev d, int g0, const 
     }
 }
 
+// FP32 version with vector operand loads.  The right-hand sides are dealt to
+// the CT = RB/16 column tiles interleaved, tile b taking columns CT*i + b, so
+// the lane that supplies column i of every tile loads its CT inputs of an
+// input row as one vector, and its CT outputs of a result row are adjacent.
+// The panel entries of a full block of 16 columns are loaded as 16 bytes per
+// lane: lane (i, q) takes row i, columns 4q .. 4q+3, which feed the four
+// steps j of the block (step j pairs column 4q + j with input row 4q + j).
+// The last, partial block of a chunk falls back to the element loads.
+template <int RB>
+__global__ __launch_bounds__(NT) void k_panel_mfma_f32(RowPanelDev d, int g0, const float *__restrict__ vals,
+                                                       const float *__restrict__ x, float *__restrict__ y,
+                                                       int accumulate)
+{
+    constexpr int CT = RB / 16;
+    __shared__ int32_t lc0[MSEG], lin[MSEG];
+    __shared__ int32_t rowidx[SK_CHUNK];
+    __shared__ float red[2][4][CT][4][64];  // two waves' partial tiles
+    const int g = g0 + blockIdx.x;
+    const int nr = d.nrows[g], nc = d.ncols[g];
+    if (nr == 0) return;  // uniform over the block
+    const int64_t off = d.val_off[g];
+    const SegMap segs = load_segments(d, g, lc0, lin);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane % 16, lq = lane / 16;
+    const int nrt = (nr + 15) / 16;  // row tiles (<= 4)
+    mf4 acc[4][CT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) acc[a][b] = mf4{0, 0, 0, 0};
+    const float *xl = x + CT * li;
+    for (int c0 = 0; c0 < nc; c0 += SK_CHUNK) {
+        const int cl = min(SK_CHUNK, nc - c0);
+        for (int c = t; c < cl; c += NT) rowidx[c] = segs.row(c0 + c);
+        __syncthreads();
+        for (int kb = 16 * wave; kb < cl; kb += 64) {
+            float av[4][4], bv[4][CT];
+            if (kb + 16 <= cl) {  // full block (uniform over the wave)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    __builtin_memcpy(bv[j], xl + (int64_t)rowidx[kb + 4 * lq + j] * RB, sizeof(float) * CT);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int r = min(16 * a + li, nr - 1);
+                    if (a < nrt)
+                        __builtin_memcpy(av[a], vals + off + (int64_t)r * nc + c0 + kb + 4 * lq, sizeof(float) * 4);
+                    else
+                        av[a][0] = av[a][1] = av[a][2] = av[a][3] = 0.0f;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = kb + 4 * lq + j;
+                    const bool kin = k < cl;
+                    const int kc = kin ? k : cl - 1;
+                    const float *xr = xl + (int64_t)rowidx[kc] * RB;
+#pragma unroll
+                    for (int b = 0; b < CT; ++b) bv[j][b] = kin ? xr[b] : 0.0f;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int r = min(16 * a + li, nr - 1);
+                        av[a][j] = (a < nrt && kin) ? vals[off + (int64_t)r * nc + c0 + kc] : 0.0f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    if (a >= nrt) continue;
+#pragma unroll
+                    for (int b = 0; b < CT; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][j], bv[j][b], acc[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // partial tiles: waves 2, 3 -> LDS, waves 0, 1 add; wave 1 -> LDS, wave 0 adds
+    if (wave >= 2)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[wave - 2][a][b][j][lane] = acc[a][b][j];
+    __syncthreads();
+    if (wave < 2)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[a][b][j] += red[wave][a][b][j][lane];
+    __syncthreads();
+    if (wave == 1)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CT; ++b)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[0][a][b][j][lane] = acc[a][b][j];
+    __syncthreads();
+    if (wave == 0) {
+        const int ob = d.out_begin[g];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            if (a >= nrt) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 16 * a + 4 * lq + j;  // FP32 16x16x4: lane (i, q) holds rows 4q + j
+                if (row >= nr) continue;
+                float v[CT], *dst = y + (int64_t)(ob + row) * RB + CT * li;
+                if (accumulate) __builtin_memcpy(v, dst, sizeof(float) * CT);
+#pragma unroll
+                for (int b = 0; b < CT; ++b) {
+                    const float s = acc[a][b][j] + red[0][a][b][j][lane];
+                    v[b] = accumulate ? v[b] + s : s;
+                }
+                __builtin_memcpy(dst, v, sizeof(float) * CT);
+            }
+        }
+    }
+}
+
 // Transposed product: Y[ob + j][:] (+)= sum_b sum_i P_b[i][c0 + j] X[in_b + i][:],
 // 64 outputs rows per pass, rows of the blocks in chunks of KC staged in LDS.
 template <typename VT, typename XT, typename YT, int ROLE, int RB>
@@ -530,6 +654,16 @@ void launch_panel_mfma(const RowPanels &rp, int g0, int g1, int rb, const T *val
     if (rp.max_nrows > 64) fail(H2B_EINVAL, "matrix-core panel product needs groups of at most 64 rows");
     if (g1 <= g0) return;
     const int acc = accumulate ? 1 : 0;
+    if constexpr (std::is_same<T, float>::value) {
+        if (rb == 16)
+            hipLaunchKernelGGL(k_panel_mfma_f32<16>, dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+        else if (rb == 32)
+            hipLaunchKernelGGL(k_panel_mfma_f32<32>, dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+        else
+            hipLaunchKernelGGL(k_panel_mfma_f32<64>, dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
+        hip_check(hipGetLastError(), "panel (matrix core, split columns) launch");
+        return;
+    }
     if (rb == 16)
         hipLaunchKernelGGL((k_panel_mfma<T, 16>), dim3(g1 - g0), dim3(NT), 0, st, rp.dev, g0, vals, x, y, acc);
     else if (rb == 32)
