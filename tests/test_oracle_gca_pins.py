@@ -115,3 +115,24 @@ def test_gca_double_layer_converges_to_the_galerkin_matrix():
         errs.append(np.linalg.norm(A @ x - K @ x) / np.linalg.norm(K @ x))
     assert errs[0] > 50 * errs[1], errs
     assert errs[1] < 1e-5, errs
+
+
+def test_gca_single_layer_symmetric_off_touching_pairs():
+    """The cross approximation of G takes its couplings from G's entries
+    between pivot triangles of admissible clusters (never touching) and uses
+    one nested basis for rows and columns, so the GCA matrix is symmetric to
+    rounding off the touching pairs, as G is; G's once-per-pair storage of
+    the GCA far field relies on this."""
+    v, t = synth.perturbed_sphere(8, 7)
+    G = oracle.slp_dense(v, t, 4)
+    touching = np.zeros((len(t), len(t)), dtype=bool)
+    for vtx in range(len(v)):
+        idx = np.nonzero((t == vtx).any(axis=1))[0]
+        touching[np.ix_(idx, idx)] = True
+    for m, eps in ((3, 1e-4), (4, 1e-8)):
+        A, info = gca.gca_dense(v, t, 16, m, eps, G)
+        assert info["far"] > 0
+        scale = np.max(np.abs(A))
+        D = np.abs(A - A.T)
+        assert np.max(D[~touching]) <= 1e-14 * scale, (m, eps)
+        assert np.max(D[touching]) <= 1e-5 * scale, (m, eps)

@@ -238,3 +238,35 @@ def test_basis_rule_exact_from_degree(kernel, m):
     a = h2.h2_rows(v, t, kernel, 16, m, rows, x)
     b = h2.h2_rows(v, t, kernel, 16, m, rows, x, q_basis=(3 * (m - 1) + 3) // 2)
     assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+def _touching(tris):
+    """Boolean matrix of the triangle pairs that share a vertex."""
+    n = len(tris)
+    T = np.zeros((n, n), dtype=bool)
+    by_vertex = {}
+    for i, tr in enumerate(tris):
+        for vtx in tr:
+            by_vertex.setdefault(int(vtx), []).append(i)
+    for lst in by_vertex.values():
+        idx = np.array(lst)
+        T[np.ix_(idx, idx)] = True
+    return T
+
+
+def test_single_layer_symmetric_off_touching_pairs():
+    """g(x, y) = g(y, x): the Galerkin entries of triangles without a common
+    vertex (both orders sum the same tensor Gauss terms) and the interpolation
+    far field (kernel values at the same pairs of points, one basis for rows
+    and columns) are symmetric to rounding.  Only touching pairs, whose
+    singular quadratures differ, break the symmetry, at quadrature error.  G's
+    once-per-pair storage of nearfield and far field relies on this."""
+    v, t = synth.perturbed_sphere(8, 7)
+    G = oracle.slp_dense(v, t, 4)
+    A, _ = h2.h2_dense(v, t, "slp", 16, 3, near_matrix=G)
+    T = _touching(t)
+    for M in (G, A):
+        scale = np.max(np.abs(M))
+        D = np.abs(M - M.T)
+        assert np.max(D[~T]) <= 1e-14 * scale
+        assert np.max(D[T]) <= 1e-5 * scale
